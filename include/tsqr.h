@@ -1,0 +1,144 @@
+/*
+ * tsqr.h -- C ABI of libtsqr.so: the R factor of a tall-skinny matrix by
+ * Householder TSQR on one AMD MI355X (gfx950) GPU.
+ *
+ * Method: J. Langou, "Computing the R of the QR factorization of tall and
+ * skinny matrices using MPI_Reduce" (arXiv:1002.4250).  The rows of A are split
+ * into blocks, each block is reduced to an n-by-n upper triangle by Householder
+ * reflections (step 1 of section 2), and the triangles are combined by the
+ * associative operator R := qr(R1, R2) of section 2 / Table 3 over a binary
+ * reduction tree (step 2; the hand-made binary tree of section 4).  On the GPU
+ * a block is the rows one wavefront streams through its on-chip triangle, and
+ * the tree runs across workgroups instead of across MPI ranks.
+ *
+ * Conventions shared by every entry point:
+ *  - Matrices are column-major: element (i, j) of a matrix with leading
+ *    dimension ld is at index i + j*ld.
+ *  - Every pointer to matrix data is a DEVICE pointer owned by the caller
+ *    (e.g. from hipMalloc or a PyTorch tensor).  The library never frees,
+ *    retains or allocates caller memory, and the compute entry points allocate
+ *    nothing: scratch space is the caller's workspace buffer.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Compute calls are asynchronous on that stream; argument checks happen
+ *    synchronously on the host before any HIP call.
+ *  - Return status: 0 = success; -k = argument k (1-based, handle counted)
+ *    is invalid and nothing was launched; positive values are the TSQR_ERR_*
+ *    codes below.
+ *  - Supported column counts: 1 <= n <= TSQR_MAX_N (n = 0 is a no-op).
+ *  - Output convention (section 2: R is unique up to row signs; fixing the
+ *    diagonal sign makes it unique): R has a non-negative diagonal and +0.0
+ *    below the diagonal.  Only the leading n-by-n block of R is written.
+ *  - Numerical range: column norms are formed as plain sums of squares in the
+ *    working precision, so entries must stay within about 1e+-150 (FP64) or
+ *    1e+-18 (FP32) of unity; a column whose remaining sum of squares is below
+ *    the smallest normal number is treated as exactly zero (identity
+ *    reflector).  NaN and Inf propagate; nothing in the hot path checks.
+ *  - Results are bit-reproducible from run to run for fixed (m, n, lda,
+ *    options): the tree pairing and the operand order of every merge are fixed.
+ */
+#ifndef TSQR_H
+#define TSQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TSQR_MAX_N 64
+
+/* element types */
+#define TSQR_F64 0
+#define TSQR_F32 1
+
+/* positive status codes */
+#define TSQR_ERR_HIP 1          /* a HIP runtime call failed: tsqr_last_hip_error() */
+#define TSQR_ERR_UNSUPPORTED 2  /* n > TSQR_MAX_N, or a size beyond the kernels' index range */
+#define TSQR_ERR_NO_DEVICE 3    /* no usable gfx950 device */
+#define TSQR_ERR_ALLOC 4        /* host or device allocation failed (plan creation only) */
+
+/* options for tsqr_set_option (0 restores the automatic choice) */
+#define TSQR_OPT_LEAF_ROWS 1      /* rows per leaf block; rounded up to a whole chunk */
+#define TSQR_OPT_ROWS_PER_LANE 2  /* rows each lane holds per chunk (chunk = 64 x this); only
+                                     compiled values take effect, others fall back */
+#define TSQR_OPT_WAVES_PER_CU 3   /* leaves per compute unit for the automatic leaf size */
+
+typedef struct tsqr_handle_s *tsqr_handle_t;
+typedef struct tsqr_batch_plan_s *tsqr_batch_plan_t;
+
+/* Create a handle bound to HIP device `device` (which becomes current on the
+ * calling thread).  Reads the device's compute-unit count for the launch
+ * policy.  Returns TSQR_ERR_NO_DEVICE if the device does not exist or is not a
+ * gfx950.  The handle owns no caller memory. */
+int tsqr_create(tsqr_handle_t *handle, int device);
+
+/* Create a planning-only handle that is bound to no device, with `cu_count`
+ * compute units assumed for the launch policy (e.g. 256 for an MI355X).  It
+ * answers tsqr_workspace_bytes and tsqr_plan_info and runs every argument
+ * check; compute calls on it return TSQR_ERR_NO_DEVICE once their arguments
+ * have been checked.  Makes no HIP call. */
+int tsqr_create_planning(tsqr_handle_t *handle, int cu_count);
+
+/* Destroy a handle (NULL is accepted). */
+int tsqr_destroy(tsqr_handle_t handle);
+
+/* The last hipError_t seen by a call on this handle (0 if none). */
+int tsqr_last_hip_error(tsqr_handle_t handle);
+
+/* Static description of a status code. */
+const char *tsqr_status_string(int status);
+
+/* Set a tuning option (see TSQR_OPT_*).  Negative values are rejected. */
+int tsqr_set_option(tsqr_handle_t handle, int option, int64_t value);
+
+/* Launch geometry tsqr_geqr_r_* will use for (m, n, dtype): rows per leaf and
+ * number of leaves (workgroups).  Either output pointer may be NULL. */
+int tsqr_plan_info(tsqr_handle_t handle, int64_t m, int64_t n, int dtype,
+                   int64_t *leaf_rows, int64_t *leaves);
+
+/* Workspace bytes needed by tsqr_geqr_r_* for (m, n, dtype) with the handle's
+ * current options (the analogue of LAPACK's lwork = -1 query, Table 1's
+ * dgeqrf call).  Returns a negative argument code on bad input, or
+ * -1000 - status for an unsupported size.  The
+ * workspace holds one packed triangle per leaf plus one tree counter per
+ * leaf; its contents on entry are irrelevant. */
+int64_t tsqr_workspace_bytes(tsqr_handle_t handle, int64_t m, int64_t n, int dtype);
+
+/* R factor of the m-by-n matrix A (the "two-line code" of Table 1 fused into
+ * one call: local Householder QR of every row block, then the reduction of
+ * the block triangles with qr_uppers over a binary tree).
+ *   A    device, m-by-n, column-major, lda >= max(1, m); read only.
+ *   R    device, n-by-n output, column-major, ldr >= max(1, n).
+ *   ws   device workspace of at least tsqr_workspace_bytes(...) bytes,
+ *        256-byte aligned; overwritten; must not be shared by calls that may
+ *        run concurrently.
+ * m = 0 gives R = 0; m < n gives zero rows m..n-1 (the missing rows are
+ * read as zeros).  Argument codes: -1 handle, -2 m, -3 n, -4 A, -5 lda, -6 R,
+ * -7 ldr, -8 ws, -9 ws_bytes. */
+int tsqr_geqr_r_f64(tsqr_handle_t handle, int64_t m, int64_t n, const double *A, int64_t lda,
+                    double *R, int64_t ldr, void *ws, int64_t ws_bytes, void *stream);
+int tsqr_geqr_r_f32(tsqr_handle_t handle, int64_t m, int64_t n, const float *A, int64_t lda,
+                    float *R, int64_t ldr, void *ws, int64_t ws_bytes, void *stream);
+
+/* The paper's reduction operator (section 3, Table 3: LILA_qr_uppers) on two
+ * n-by-n upper triangles stacked as [R1; R2], same contract:
+ *   R1   device, n-by-n, leading dimension n; on exit its upper triangle holds
+ *        R (diagonal signs as the reflectors leave them: no normalisation).
+ *   R2   device, n-by-n, leading dimension n; on exit its upper triangle holds
+ *        the Householder vectors V, the reflectors being H_j = I - tau_j
+ *        [e_j; V(:,j)] [e_j; V(:,j)]^T.
+ *   tau  device, n scalars.
+ * Only the upper triangles of R1 and R2 are read or written.  One workgroup
+ * computes the operator; the call is latency-bound by design.  Argument
+ * codes: -1 handle, -2 n, -3 R1, -4 R2, -5 tau. */
+int tsqr_qr_uppers_f64(tsqr_handle_t handle, int64_t n, double *R1, double *R2, double *tau,
+                       void *stream);
+int tsqr_qr_uppers_f32(tsqr_handle_t handle, int64_t n, float *R1, float *R2, float *tau,
+                       void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSQR_H */

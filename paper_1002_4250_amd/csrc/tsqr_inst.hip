@@ -1,0 +1,50 @@
+// tsqr_inst.hip -- one kernel instantiation of libtsqr.so, selected at compile
+// time: -DTSQR_INST_LEAF -DTSQR_INST_TAG=f64|f32 -DTSQR_INST_NC=<n> -DTSQR_INST_RPL=<r>
+// for a leaf+tree kernel, -DTSQR_INST_OP with TAG and NC for an operator
+// kernel, or -DTSQR_INST_COMMON for the small helper kernels.
+#include "tsqr_device.h"
+#include "tsqr_internal.h"
+
+
+namespace tsqr {
+
+#if defined(TSQR_INST_LEAF)
+#define TSQR_LEAF_FN(tag, nc, rpl) launch_leaf_tree_##tag##_##nc##_##rpl
+#define TSQR_LEAF_FN2(tag, nc, rpl) TSQR_LEAF_FN(tag, nc, rpl)
+hipError_t TSQR_LEAF_FN2(TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL)(const LeafTreeArgs<TSQR_INST_TAG>& a,
+                                                                     hipStream_t s)
+{
+    hipLaunchKernelGGL((dev::tsqr_leaf_tree_kernel<TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL>), dim3(a.leaves),
+                       dim3(dev::kWave), 0, s, a);
+    return hipGetLastError();
+}
+#elif defined(TSQR_INST_OP)
+#define TSQR_OP_FN(tag, nc) launch_qr_uppers_##tag##_##nc
+#define TSQR_OP_FN2(tag, nc) TSQR_OP_FN(tag, nc)
+hipError_t TSQR_OP_FN2(TSQR_INST_TAG, TSQR_INST_NC)(int n, TSQR_INST_TAG* R1, TSQR_INST_TAG* R2,
+                                                    TSQR_INST_TAG* tau, hipStream_t s)
+{
+    hipLaunchKernelGGL((dev::qr_uppers_kernel<TSQR_INST_TAG, TSQR_INST_NC>), dim3(1), dim3(dev::kWave), 0, s, n,
+                       R1, R2, tau);
+    return hipGetLastError();
+}
+#elif defined(TSQR_INST_COMMON)
+namespace dev {
+__global__ void zero_u32_kernel(unsigned* p, int count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0u;
+}
+}  // namespace dev
+
+hipError_t launch_zero_u32(unsigned* p, int count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dev::zero_u32_kernel, dim3((count + 255) / 256), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+#else
+#error "select an instantiation with -DTSQR_INST_LEAF, -DTSQR_INST_OP or -DTSQR_INST_COMMON"
+#endif
+
+}  // namespace tsqr

@@ -1,0 +1,217 @@
+"""Python binding of libtsqr.so (ctypes): argument marshalling only.
+
+Every function of include/tsqr.h is exposed under the same name with the same
+arguments (device pointers and streams passed as integers).  Convenience
+wrappers that take PyTorch tensors -- :func:`geqr_r`, :func:`qr_uppers` --
+only read ``data_ptr()``/strides and the current HIP stream, allocate the
+output and the workspace with torch, and call the C entry points; every step of
+the computation runs in the library's HIP kernels.  There is no fallback: if
+the library is missing or no gfx950 device is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libtsqr.so")
+
+TSQR_MAX_N = 64
+TSQR_F64 = 0
+TSQR_F32 = 1
+TSQR_ERR_HIP = 1
+TSQR_ERR_UNSUPPORTED = 2
+TSQR_ERR_NO_DEVICE = 3
+TSQR_ERR_ALLOC = 4
+TSQR_OPT_LEAF_ROWS = 1
+TSQR_OPT_ROWS_PER_LANE = 2
+TSQR_OPT_WAVES_PER_CU = 3
+
+# (name, restype, argtypes) for every exported symbol of include/tsqr.h
+_i, _i64, _p, _pi64 = ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
+SIGNATURES = [
+    ("tsqr_create", _i, [ctypes.POINTER(_p), _i]),
+    ("tsqr_create_planning", _i, [ctypes.POINTER(_p), _i]),
+    ("tsqr_destroy", _i, [_p]),
+    ("tsqr_last_hip_error", _i, [_p]),
+    ("tsqr_status_string", ctypes.c_char_p, [_i]),
+    ("tsqr_set_option", _i, [_p, _i, _i64]),
+    ("tsqr_plan_info", _i, [_p, _i64, _i64, _i, _pi64, _pi64]),
+    ("tsqr_workspace_bytes", _i64, [_p, _i64, _i64, _i]),
+    ("tsqr_geqr_r_f64", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
+    ("tsqr_geqr_r_f32", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
+    ("tsqr_qr_uppers_f64", _i, [_p, _i64, _p, _p, _p, _p]),
+    ("tsqr_qr_uppers_f32", _i, [_p, _i64, _p, _p, _p, _p]),
+]
+
+_LOCK = threading.Lock()
+_LIB = None
+
+
+class TsqrError(RuntimeError):
+    def __init__(self, fn: str, status: int, hip_error: int = 0):
+        msg = f"{fn} returned {status}"
+        if _LIB is not None:
+            msg += " (" + _LIB.tsqr_status_string(status).decode() + ")"
+        if hip_error:
+            msg += f", hipError {hip_error}"
+        super().__init__(msg)
+        self.status = status
+
+
+def load(path: str = LIB_PATH):
+    """Load libtsqr.so and declare its signatures (raises if it is missing)."""
+    global _LIB
+    with _LOCK:
+        if _LIB is None:
+            if not os.path.exists(path):
+                raise FileNotFoundError(
+                    f"{path} is missing: build it with `python -m paper_1002_4250_amd.build`")
+            lib = ctypes.CDLL(path)
+            for name, res, args in SIGNATURES:
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+            _LIB = lib
+        return _LIB
+
+
+def lib():
+    return load()
+
+
+def _check(fn: str, status: int, handle=None):
+    if status != 0:
+        he = lib().tsqr_last_hip_error(handle) if handle else 0
+        raise TsqrError(fn, status, he)
+
+
+# ---- the C entry points under their own names -------------------------------
+
+def tsqr_create(device: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check("tsqr_create", lib().tsqr_create(ctypes.byref(h), int(device)))
+    return h.value
+
+
+def tsqr_create_planning(cu_count: int = 256) -> int:
+    h = ctypes.c_void_p()
+    _check("tsqr_create_planning", lib().tsqr_create_planning(ctypes.byref(h), int(cu_count)))
+    return h.value
+
+
+def tsqr_destroy(handle: int) -> None:
+    lib().tsqr_destroy(handle)
+
+
+def tsqr_set_option(handle: int, option: int, value: int) -> None:
+    _check("tsqr_set_option", lib().tsqr_set_option(handle, int(option), int(value)), handle)
+
+
+def tsqr_plan_info(handle: int, m: int, n: int, dtype: int):
+    lr, lv = ctypes.c_int64(), ctypes.c_int64()
+    _check("tsqr_plan_info", lib().tsqr_plan_info(handle, m, n, dtype, ctypes.byref(lr), ctypes.byref(lv)), handle)
+    return lr.value, lv.value
+
+
+def tsqr_workspace_bytes(handle: int, m: int, n: int, dtype: int) -> int:
+    v = lib().tsqr_workspace_bytes(handle, int(m), int(n), int(dtype))
+    if v < 0:
+        raise TsqrError("tsqr_workspace_bytes", int(v))
+    return int(v)
+
+
+def tsqr_geqr_r_f64(handle, m, n, A, lda, R, ldr, ws, ws_bytes, stream) -> int:
+    return lib().tsqr_geqr_r_f64(handle, m, n, A, lda, R, ldr, ws, ws_bytes, stream)
+
+
+def tsqr_geqr_r_f32(handle, m, n, A, lda, R, ldr, ws, ws_bytes, stream) -> int:
+    return lib().tsqr_geqr_r_f32(handle, m, n, A, lda, R, ldr, ws, ws_bytes, stream)
+
+
+def tsqr_qr_uppers_f64(handle, n, R1, R2, tau, stream) -> int:
+    return lib().tsqr_qr_uppers_f64(handle, n, R1, R2, tau, stream)
+
+
+def tsqr_qr_uppers_f32(handle, n, R1, R2, tau, stream) -> int:
+    return lib().tsqr_qr_uppers_f32(handle, n, R1, R2, tau, stream)
+
+
+# ---- torch convenience layer ----------------------------------------------------
+
+_HANDLES = {}
+
+
+def handle(device: int = 0) -> int:
+    """A process-wide handle per device (created on first use)."""
+    with _LOCK:
+        h = _HANDLES.get(device)
+    if h is None:
+        h = tsqr_create(device)
+        with _LOCK:
+            _HANDLES[device] = h
+    return h
+
+
+def _stream_ptr(torch, dev):
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def _col_major(A):
+    """(m, n, lda) of a column-major 2-D tensor (stride (1, lda))."""
+    m, n = A.shape
+    s0, s1 = A.stride()
+    if s0 != 1 and m > 1:
+        raise ValueError("A must be column-major: A.stride(0) == 1 (use A.t().contiguous().t())")
+    lda = max(s1, max(m, 1)) if n > 1 else max(m, 1)
+    return m, n, lda
+
+
+def workspace(m: int, n: int, dtype, device=None, h=None):
+    """A uint8 workspace tensor large enough for geqr_r(m, n)."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    h = h or handle(dev.index or 0)
+    code = TSQR_F64 if dtype == torch.float64 else TSQR_F32
+    nbytes = tsqr_workspace_bytes(h, m, n, code)
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+
+
+def geqr_r(A, R=None, ws=None, h=None):
+    """R factor (n-by-n, diag >= 0, column-major) of the column-major device
+    matrix A (float64 or float32) by TSQR on the GPU."""
+    import torch
+    if A.dtype not in (torch.float64, torch.float32):
+        raise TypeError("A must be float64 or float32")
+    if not A.is_cuda:
+        raise ValueError("A must be a device tensor")
+    m, n, lda = _col_major(A)
+    dev = A.device
+    h = h or handle(dev.index or 0)
+    if R is None:
+        R = torch.empty((n, n), dtype=A.dtype, device=dev).t()   # column-major n x n
+    ldr = R.stride(1) if n > 1 else max(n, 1)
+    if ws is None:
+        ws = workspace(m, n, A.dtype, dev, h)
+    fn = tsqr_geqr_r_f64 if A.dtype == torch.float64 else tsqr_geqr_r_f32
+    st = fn(h, m, n, A.data_ptr(), lda, R.data_ptr(), ldr, ws.data_ptr(), ws.numel(), _stream_ptr(torch, dev))
+    _check(fn.__name__, st, h)
+    return R
+
+
+def qr_uppers(R1, R2, tau=None, h=None):
+    """The paper's operator in place on column-major n-by-n device tensors:
+    R1 <- R, R2 <- V, tau <- reflector scalars.  Returns (R1, R2, tau)."""
+    import torch
+    n = R1.shape[0]
+    for X in (R1, R2):
+        if X.shape != (n, n) or (n > 1 and X.stride() != (1, n)):
+            raise ValueError("R1 and R2 must be n-by-n column-major with leading dimension n")
+    h = h or handle(R1.device.index or 0)
+    if tau is None:
+        tau = torch.empty(max(n, 1), dtype=R1.dtype, device=R1.device)
+    fn = tsqr_qr_uppers_f64 if R1.dtype == torch.float64 else tsqr_qr_uppers_f32
+    st = fn(h, n, R1.data_ptr(), R2.data_ptr(), tau.data_ptr(), _stream_ptr(torch, R1.device))
+    _check(fn.__name__, st, h)
+    return R1, R2, tau[:n]

@@ -1,0 +1,130 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+function include/tsqr.h declares, and its planning and argument checks behave
+as documented."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1002_4250_amd import tsqr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tsqr.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tsqr_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(tsqr.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    # the binding declares exactly the header's functions
+    assert sorted(n for n, _, _ in tsqr.SIGNATURES) == names
+
+
+def test_header_constants_match_binding():
+    text = open(HEADER).read()
+    for name in ("TSQR_MAX_N", "TSQR_F64", "TSQR_F32", "TSQR_ERR_HIP", "TSQR_ERR_UNSUPPORTED",
+                 "TSQR_ERR_NO_DEVICE", "TSQR_ERR_ALLOC", "TSQR_OPT_LEAF_ROWS", "TSQR_OPT_ROWS_PER_LANE",
+                 "TSQR_OPT_WAVES_PER_CU"):
+        m = re.search(r"#define\s+%s\s+(\d+)" % name, text)
+        assert m and int(m.group(1)) == getattr(tsqr, name), name
+
+
+@pytest.fixture
+def ph():
+    h = tsqr.tsqr_create_planning(256)
+    yield h
+    tsqr.tsqr_destroy(h)
+
+
+def test_null_handle_is_argument_one():
+    L = tsqr.lib()
+    assert L.tsqr_geqr_r_f64(None, 10, 2, None, 10, None, 2, None, 0, None) == -1
+    assert L.tsqr_qr_uppers_f32(None, 4, None, None, None, None) == -1
+    assert L.tsqr_workspace_bytes(None, 10, 2, 0) == -1
+    assert L.tsqr_create(None, 0) == -1
+    assert L.tsqr_set_option(None, 1, 0) == -1
+
+
+def test_status_strings():
+    assert tsqr.lib().tsqr_status_string(0) == b"success"
+    assert b"invalid" in tsqr.lib().tsqr_status_string(-3)
+    assert b"gfx950" in tsqr.lib().tsqr_status_string(tsqr.TSQR_ERR_NO_DEVICE)
+
+
+def test_argument_checks_in_order(ph):
+    L = tsqr.lib()
+    f = L.tsqr_geqr_r_f64
+    A, R, W = 4096, 8192, 256 * 1024
+    assert f(ph, -1, 5, A, 10, R, 5, W, 1 << 30, None) == -2
+    assert f(ph, 10, -1, A, 10, R, 5, W, 1 << 30, None) == -3
+    assert f(ph, 10, 5, None, 10, R, 5, W, 1 << 30, None) == -4
+    assert f(ph, 10, 5, A, 9, R, 5, W, 1 << 30, None) == -5
+    assert f(ph, 10, 5, A, 10, None, 5, W, 1 << 30, None) == -6
+    assert f(ph, 10, 5, A, 10, R, 4, W, 1 << 30, None) == -7
+    assert f(ph, 10, 5, A, 10, R, 5, None, 1 << 30, None) == -8
+    assert f(ph, 10, 5, A, 10, R, 5, W + 8, 1 << 30, None) == -8      # misaligned workspace
+    need = tsqr.tsqr_workspace_bytes(ph, 10, 5, tsqr.TSQR_F64)
+    assert f(ph, 10, 5, A, 10, R, 5, W, need - 1, None) == -9
+    # all arguments valid: a planning handle stops before any HIP call
+    assert f(ph, 10, 5, A, 10, R, 5, W, need, None) == tsqr.TSQR_ERR_NO_DEVICE
+    assert f(ph, 10, 65, A, 10, R, 65, W, 1 << 30, None) == tsqr.TSQR_ERR_UNSUPPORTED
+    assert f(ph, 10, 0, None, 10, None, 1, None, 0, None) == 0          # n = 0 is a no-op
+    g = L.tsqr_qr_uppers_f64
+    assert g(ph, -1, R, R, R, None) == -2
+    assert g(ph, 3, None, R, R, None) == -3
+    assert g(ph, 3, R, None, R, None) == -4
+    assert g(ph, 3, R, R, None, None) == -5
+    assert g(ph, 65, R, R, R, None) == tsqr.TSQR_ERR_UNSUPPORTED
+    assert g(ph, 3, R, R, R, None) == tsqr.TSQR_ERR_NO_DEVICE
+
+
+def test_plan_geometry(ph):
+    # m = 2^22, n = 50 in FP64: leaves of whole chunks, about 4 per compute unit
+    lr, P = tsqr.tsqr_plan_info(ph, 1 << 22, 50, tsqr.TSQR_F64)
+    assert lr * P >= 1 << 22 and lr * (P - 1) < 1 << 22
+    assert 256 * 2 <= P <= 256 * 8
+    chunk = 64 * 2
+    assert lr % chunk == 0
+    ws = tsqr.tsqr_workspace_bytes(ph, 1 << 22, 50, tsqr.TSQR_F64)
+    assert ws >= P * 4 + P * (50 * 51 // 2) * 8 and ws % 256 == 0
+    # tiny m: one leaf of one chunk
+    lr, P = tsqr.tsqr_plan_info(ph, 1, 3, tsqr.TSQR_F32)
+    assert P == 1 and lr == 64 * 4
+    # forced leaf size, rounded up to a chunk
+    tsqr.tsqr_set_option(ph, tsqr.TSQR_OPT_LEAF_ROWS, 100)
+    lr, P = tsqr.tsqr_plan_info(ph, 1000, 50, tsqr.TSQR_F64)
+    assert lr == 128 and P == 8
+    tsqr.tsqr_set_option(ph, tsqr.TSQR_OPT_LEAF_ROWS, 0)
+    # m = 0 still has one (empty) leaf so that R = 0 is written
+    assert tsqr.tsqr_plan_info(ph, 0, 7, tsqr.TSQR_F64)[1] == 1
+    with pytest.raises(tsqr.TsqrError):
+        tsqr.tsqr_plan_info(ph, 10, 65, tsqr.TSQR_F64)
+    assert tsqr.lib().tsqr_set_option(ph, 99, 1) == -2
+    assert tsqr.lib().tsqr_set_option(ph, 1, -5) == -3
+
+
+def test_workspace_query_errors(ph):
+    L = tsqr.lib()
+    assert L.tsqr_workspace_bytes(ph, -1, 5, 0) == -2
+    assert L.tsqr_workspace_bytes(ph, 5, -1, 0) == -3
+    assert L.tsqr_workspace_bytes(ph, 5, 5, 7) == -4
+    assert L.tsqr_workspace_bytes(ph, 5, 0, 0) == 0
+    assert L.tsqr_workspace_bytes(ph, 5, 65, 0) == -1000 - tsqr.TSQR_ERR_UNSUPPORTED
+
+
+def test_create_without_gpu_reports_no_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert tsqr.lib().tsqr_create(ctypes.byref(h), 0) == tsqr.TSQR_ERR_NO_DEVICE
+    assert not h.value
