@@ -100,10 +100,10 @@ int tsqr_plan_info(tsqr_handle_t handle, int64_t m, int64_t n, int dtype,
 /* Workspace bytes needed by tsqr_geqr_r_* for (m, n, dtype) with the handle's
  * current options (the analogue of LAPACK's lwork = -1 query, Table 1's
  * dgeqrf call).  Returns a negative argument code on bad input, or
- * -1000 - status for an unsupported size.  The
- * workspace holds one packed triangle per leaf plus one tree counter per
- * leaf; its contents on entry are irrelevant. */
+ * -1000 - status for an unsupported size.  The workspace holds one tree
+ * counter per leaf (at its start) and one packed triangle per leaf. */
 int64_t tsqr_workspace_bytes(tsqr_handle_t handle, int64_t m, int64_t n, int dtype);
+
 
 /* R factor of the m-by-n matrix A (the "two-line code" of Table 1 fused into
  * one call: local Householder QR of every row block, then the reduction of
@@ -111,8 +111,11 @@ int64_t tsqr_workspace_bytes(tsqr_handle_t handle, int64_t m, int64_t n, int dty
  *   A    device, m-by-n, column-major, lda >= max(1, m); read only.
  *   R    device, n-by-n output, column-major, ldr >= max(1, n).
  *   ws   device workspace of at least tsqr_workspace_bytes(...) bytes,
- *        256-byte aligned; overwritten; must not be shared by calls that may
- *        run concurrently.
+ *        256-byte aligned; contents on entry are irrelevant and are
+ *        overwritten; calls that may run concurrently must not share a
+ *        workspace.
+ * The call makes two kernel launches (a small one that zeroes the tree
+ * counters, then the factorisation) and allocates nothing.
  * m = 0 gives R = 0; m < n gives zero rows m..n-1 (the missing rows are
  * read as zeros).  Argument codes: -1 handle, -2 m, -3 n, -4 A, -5 lda, -6 R,
  * -7 ldr, -8 ws, -9 ws_bytes. */

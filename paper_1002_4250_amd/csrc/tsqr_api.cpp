@@ -22,7 +22,7 @@ struct tsqr_handle_s {
 
 namespace {
 
-constexpr int kWave = 64;
+constexpr int kRowsPerLaneUnit = 16;   // a chunk is 16 * rows-per-lane rows (16 lanes share a column)
 constexpr int64_t kAlign = 256;
 
 int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -55,7 +55,7 @@ struct Geometry {
     int64_t ws_bytes = 0;
 };
 
-// Leaf policy: a chunk is 64*RPL rows; the automatic leaf size gives about
+// Leaf policy: a chunk is 16*RPL rows; the automatic leaf size gives about
 // waves_per_cu leaves per compute unit (each leaf is one wavefront), never
 // less than one chunk.  The tree then has ceil(log2 P) levels.
 int plan(const tsqr_handle_s* h, int64_t m, int64_t n, int dtype, Geometry* g)
@@ -68,7 +68,7 @@ int plan(const tsqr_handle_s* h, int64_t m, int64_t n, int dtype, Geometry* g)
         g->rpl = dtype == TSQR_F64 ? TSQR_DEFAULT_RPL_F64 : TSQR_DEFAULT_RPL_F32;
         if (!leaf_instance_exists(dtype, g->nc, g->rpl)) return TSQR_ERR_UNSUPPORTED;
     }
-    const int64_t chunk = (int64_t)kWave * g->rpl;
+    const int64_t chunk = (int64_t)kRowsPerLaneUnit * g->rpl;
     int64_t L;
     if (h->leaf_rows > 0) {
         L = align_up(h->leaf_rows, chunk);
@@ -154,6 +154,9 @@ int geqr_r(tsqr_handle_t h, int64_t m, int64_t n, const T* A, int64_t lda, T* R,
     a.R = R;
     a.ldr = ldr;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    // the tree counters are zeroed by a kernel on every call: their position
+    // depends on the leaf count, so a previous call with another leaf count may
+    // have left triangle data there
     hipError_t e = tsqr::launch_zero_u32(a.tickets, a.leaves, s);
     if (e == hipSuccess) e = dispatch_leaf<T>(a, g.nc, g.rpl, s);
     return hip_status(h, e);

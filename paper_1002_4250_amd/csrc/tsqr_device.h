@@ -4,13 +4,11 @@
 // Execution model (one wavefront of 64 lanes per workgroup):
 //   * A leaf is a contiguous block of rows of A.  Its wavefront keeps the n-by-n
 //     triangle R in LDS (packed by rows) and streams the block through
-//     registers in chunks of 64*RPL rows; chunk rows are distributed one per
-//     lane per register slot (lane l holds rows base + l + 64*r, r < RPL, all
-//     NC columns).  Each chunk C is merged into R by R := R-factor of [R; C]:
-//     for every column j one Householder reflector built from R(j,j) and
-//     C(:,j) is applied to the trailing columns (the structured update of
-//     Table 3 with R2 replaced by a dense chunk: a flat tree inside the leaf,
-//     section 2 allows any tree).
+//     registers in chunks of 16*RPL rows.  Each chunk C is merged into R by
+//     R := R-factor of [R; C]: for every column j one Householder reflector
+//     built from R(j,j) and C(:,j) is applied to the trailing columns (the
+//     structured update of Table 3 with R2 replaced by a dense chunk: a flat
+//     tree inside the leaf; section 2 allows any tree).
 //   * Leaves then combine with the paper's operator qr(R1, R2) over a binary
 //     tree pairing leaf i with i + 2^level (lower index on top), the merge done
 //     by whichever wavefront of the pair arrives last (atomic ticket), so no
@@ -18,21 +16,23 @@
 //   * The root flips rows with a negative diagonal (section 2's positive
 //     diagonal convention) and writes R.
 //
-// Per Householder step j (K = NC-1-j trailing columns, x = C(:,j)):
-//     d_0 = x.x, d_v = x.C(:,j+v)                 (partials in registers, then a
-//                                                  64-lane transpose-reduction)
-//     beta = -sign(alpha) sqrt(alpha^2 + d_0), alpha = R(j,j)
+// Register layout of a chunk: the wavefront is four 16-lane rows q = 0..3.
+// Lane (q, p) = lane 16q + p holds chunk rows p + 16r (r < RPL) of the
+// columns k = 4s + q (slot s < NS = ceil(NC/4)): the columns are dealt
+// cyclically to the four lane rows, the matrix rows to the 16 lanes of a lane
+// row.  A dot product over the chunk's rows is then a sum over RPL registers
+// and over only 16 lanes, which goes through LDS in one transpose (each lane
+// adds 16 values); the pivot column reaches all lane rows by one ds_bpermute
+// per register.
+//
+// Per Householder step j (x = C(:,j), k > j the trailing columns):
+//     sigma^2 = x.x,  d_k = x.C(:,k)
+//     beta = -sign(alpha) sqrt(alpha^2 + sigma^2), alpha = R(j,j)
 //     tau = (beta - alpha)/beta, s = 1/(alpha - beta)        (v = s x)
-//     w_v = R(j,j+v) + s d_v,  R(j,j+v) -= tau w_v,  C(:,j+v) -= (tau s w_v) x
+//     w_k = R(j,k) + s d_k,  R(j,k) -= tau w_k,  C(:,k) -= (tau s w_k) x
 // which is the reflector generation and rank-1 update of Table 3 with the
 // Householder vector kept unscaled (v = s x) so that no lane has to rescale
 // its rows before the dot products.
-//
-// The transpose-reduction of V = K+1 values uses the gfx950 lane-swap
-// instructions: v_permlane32_swap pairs values (2q, 2q+1) across the two
-// 32-lane halves, v_permlane16_swap pairs the results across 16-lane rows,
-// and the last 16-to-1 sum goes through LDS, after which lane 16*r + p holds
-// the full sum of value 4p + 2(r&1) + (r>>1).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -49,17 +49,18 @@ namespace dev {
 
 constexpr int kWave = 64;
 constexpr int kRedStride = 17;                  // odd stride: conflict-free LDS transpose
-constexpr int kRedElems = 4 * 16 * kRedStride;
-#ifndef TSQR_GROUP
-#define TSQR_GROUP 8
-#endif
-constexpr int kGroup = TSQR_GROUP;              // update coefficients read per group
+constexpr int kRedElems = 4 * 16 * kRedStride;  // one 16 x 17 tile per lane row
 
 template <int NC>
 struct Tri {
     static constexpr int kSize = NC * (NC + 1) / 2;
     // packed row-major upper triangle: row j starts at off(j), entry (j,k) at off(j)+k-j
     static constexpr __host__ __device__ int off(int j) { return j * NC - (j * (j - 1)) / 2; }
+};
+
+template <int NC>
+struct Slots {
+    static constexpr int NS = (NC + 3) / 4;     // column slots per lane
 };
 
 template <int I, int N, typename F>
@@ -77,275 +78,301 @@ template <> struct Limits<float> { static constexpr float tiny = 1.17549435e-38f
 
 // ---- cross-lane primitives -------------------------------------------------
 
-// Lanes 0-31 return a(l) + a(l+32); lanes 32-63 return b(l-32) + b(l).
-__device__ __forceinline__ double pair32(double a, double b)
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x)
 {
-    unsigned alo = (unsigned)__double2loint(a), ahi = (unsigned)__double2hiint(a);
-    unsigned blo = (unsigned)__double2loint(b), bhi = (unsigned)__double2hiint(b);
-    auto lo = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
-    auto hi = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
-    return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
-}
-__device__ __forceinline__ float pair32(float a, float b)
-{
-    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
-    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
-// Within each pair of 16-lane rows (0,1) and (2,3): even rows return a summed
-// over the two rows, odd rows return b summed over the two rows.
-__device__ __forceinline__ double pair16(double a, double b)
-{
-    unsigned alo = (unsigned)__double2loint(a), ahi = (unsigned)__double2hiint(a);
-    unsigned blo = (unsigned)__double2loint(b), bhi = (unsigned)__double2hiint(b);
-    auto lo = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
-    auto hi = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
-    return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
-}
-__device__ __forceinline__ float pair16(float a, float b)
-{
-    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
-    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
-
-__device__ __forceinline__ double readlane(double x, int l)
-{
-    int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
-    int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+    int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ float readlane(float x, int l)
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x)
 {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the 16 lanes of each lane row, returned in all 16 (bit-identical).
+template <typename T>
+__device__ __forceinline__ T row_allreduce16(T x)
+{
+    x = x + dpp_mov<0x128>(x);   // row_ror:8
+    x = x + dpp_mov<0x124>(x);   // row_ror:4
+    x = x + dpp_mov<0x122>(x);   // row_ror:2
+    x = x + dpp_mov<0x121>(x);   // row_ror:1
+    return x;
+}
+
+// Value of x held by the lane whose byte address (4 * lane) is src.
+__device__ __forceinline__ double bpermute(int src, double x)
+{
+    int lo = __builtin_amdgcn_ds_bpermute(src, __double2loint(x));
+    int hi = __builtin_amdgcn_ds_bpermute(src, __double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float bpermute(int src, float x)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(x)));
 }
 
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }
 
-// Lane that holds reduced value v after transpose_reduce.
-__host__ __device__ constexpr int holder_lane(int v)
+// Orders this wavefront's LDS accesses around a point without constraining
+// arithmetic: LDS operations of one wavefront execute in order, so only the
+// compiler has to be kept from moving them across.
+__device__ __forceinline__ void lds_order()
 {
-    return 16 * (((v & 1) << 1) | ((v >> 1) & 1)) + (v >> 2);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---- reflector scalars ---------------------------------------------------------
+
+// With S = alpha^2 + sigma^2, nrm = sqrt(S) and sgn = sign(alpha) read from its
+// sign bit:
+//     beta = -sgn nrm,  tau = (beta - alpha)/beta = (|alpha| + nrm)/nrm,
+//     s = 1/(alpha - beta) = sgn/(|alpha| + nrm),  tau*s = sgn/nrm.
+// 1/nrm comes from the hardware reciprocal square root refined by two Newton
+// steps, nrm = S/sqrt(S) with one Newton correction, 1/(|alpha| + nrm) from the
+// hardware reciprocal with two Newton steps: a short dependent chain instead
+// of two IEEE divisions and a square root.  A column whose sigma^2 is below
+// the smallest normal number gives the identity reflector.
+template <typename T>
+struct Reflector {
+    T beta, tau, s, ts;
+};
+
+__device__ __forceinline__ double hw_rsq(double x) { return __builtin_amdgcn_rsq(x); }
+__device__ __forceinline__ float hw_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double hw_rcp(double x) { return __builtin_amdgcn_rcp(x); }
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+template <typename T>
+__device__ __forceinline__ Reflector<T> make_reflector(T alpha, T sigma2)
+{
+    const T S = __builtin_fma(alpha, alpha, sigma2);
+    T y = hw_rsq(S);
+    const T hS = T(0.5) * S;
+#pragma unroll
+    for (int it = 0; it < 2; ++it) y = __builtin_fma(y, __builtin_fma(-hS * y, y, T(0.5)), y);
+    T nrm = S * y;
+    nrm = __builtin_fma(T(0.5) * y, __builtin_fma(-nrm, nrm, S), nrm);
+    const T d = __builtin_fabs(alpha) + nrm;
+    T q = hw_rcp(d);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) q = __builtin_fma(q, __builtin_fma(-d, q, T(1)), q);
+    const bool neg = __builtin_signbit(alpha);
+    const bool ok = sigma2 >= Limits<T>::tiny;
+    Reflector<T> r;
+    r.beta = ok ? (neg ? nrm : -nrm) : alpha;
+    r.tau = ok ? d * y : T(0);
+    r.s = ok ? (neg ? -q : q) : T(0);
+    r.ts = ok ? (neg ? -y : y) : T(0);
+    return r;
 }
 
 // ---- one Householder step ----------------------------------------------------
 
 enum class Mode { Leaf, Merge, Operator };
 
-// Where a leaf prefetches its next chunk from: a running pointer to column J
-// of the next chunk, advanced by lda after every step.  lda and the column
-// count pass through an opaque register copy at every chunk so that the
-// compiler keeps one running pointer instead of precomputing (and keeping
-// live) one address and one predicate per column.
+// Where a leaf prefetches its next chunk from.  A register slot holds four
+// columns (one per lane row); once its four columns are finished (after step
+// 4s+3) the whole slot is refilled with the next chunk's columns 4s..4s+3 by
+// one wavefront-wide load per register, into registers no later step of the
+// current chunk reads, so no step waits for the loads.  `col` is a per-lane
+// running pointer to the lane's column of the next slot; lda and n pass
+// through an opaque register copy so the compiler keeps that one pointer
+// instead of precomputing one address per slot.
 template <typename T, int RPL>
 struct Prefetch {
-    const T* col;        // uniform: &A(base, J)
-    int64_t lda;         // uniform
-    int cols_left;       // uniform: columns J..n-1 still to load
-    bool ok[RPL];        // per lane: row base + lane + 64 r lies inside the leaf
+    const T* col;        // per lane: &A(base, 4s + q) for the next slot s to fill
+    int64_t lda4;        // uniform: 4 * lda
+    int cols_left;       // per lane: n - (4s + q)
+    bool ok[RPL];        // per lane: row base + p + 16 r lies inside the leaf
 };
 
 template <typename T, int RPL>
 __device__ __forceinline__ Prefetch<T, RPL> make_prefetch(const T* A, int64_t lda, int n, int64_t base, int64_t r1,
-                                                          int lane)
+                                                          int q, int p)
 {
     Prefetch<T, RPL> pf;
     int64_t ld = lda;
     int nn = n;
     asm volatile("" : "+s"(ld), "+s"(nn));
-    pf.col = A + (base < r1 ? base : 0);
-    pf.lda = ld;
-    pf.cols_left = nn;
+    pf.col = A + (base < r1 ? base : 0) + (int64_t)q * ld;
+    pf.lda4 = 4 * ld;
+    pf.cols_left = nn - q;
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) pf.ok[r] = base + lane + kWave * r < r1;
+    for (int r = 0; r < RPL; ++r) pf.ok[r] = base + p + 16 * r < r1;
     return pf;
 }
 
-template <typename T, int NC, int RPL>
-__device__ __forceinline__ void prefetch_column(T (&c)[RPL][NC], int J, Prefetch<T, RPL>& pf, int lane)
-{
-    if (pf.cols_left > 0) {
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) c[r][J] = pf.ok[r] ? pf.col[lane + kWave * r] : T(0);
-    } else {
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) c[r][J] = T(0);
-    }
-    pf.col += pf.lda;
-    pf.cols_left -= 1;
-}
-
-// Step J of R := qr([R; C]) with R packed in LDS (Rs) and C in registers.
+// Step J of R := qr([R; C]) with R packed in LDS (Rs) and C in registers.  The
+// NC steps of a chunk are unrolled at compile time so every register index is
+// static and the scheduler can overlap consecutive steps.
 template <typename T, int NC, int RPL, Mode M, int J>
-__device__ __forceinline__ void hh_step(T (&c)[RPL][NC], T* Rs, T* red, T* F, int lane,
+__device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* red, T* F, int q, int p,
                                         Prefetch<T, RPL>& pf, T* tau_out)
 {
-    constexpr int K = NC - 1 - J;
-    constexpr int V = K + 1;
-    constexpr int HA = (V + 1) / 2;
-    constexpr int HB = (HA + 1) / 2;
+    constexpr int NS = Slots<NC>::NS;
+    constexpr int QJ = J % 4, SJ = J / 4;     // lane row and slot holding column J
+    constexpr int K = NC - 1 - J;             // trailing columns
     constexpr int OFF = Tri<NC>::off(J);
 
-    auto dot = [&](auto vc) -> T {
-        constexpr int v = decltype(vc)::value;
-        if constexpr (v >= V) {
-            return T(0);
-        } else {
-            T s = c[0][J] * c[0][J + v];
+    // (a) the pivot column in every lane row, its norm and reflector
+    const int src = ((QJ << 4) | p) << 2;
+    T x[RPL];
 #pragma unroll
-            for (int r = 1; r < RPL; ++r) s = __builtin_fma(c[r][J], c[r][J + v], s);
-            return s;
-        }
-    };
-
-    // stages A and B, fused with the production of the partial dot products
-    T b[HB];
-    static_for<0, HB>([&](auto tc) {
-        constexpr int t = decltype(tc)::value;
-        T a0 = pair32(dot(std::integral_constant<int, 4 * t>{}), dot(std::integral_constant<int, 4 * t + 1>{}));
-        T a1 = pair32(dot(std::integral_constant<int, 4 * t + 2>{}), dot(std::integral_constant<int, 4 * t + 3>{}));
-        b[t] = pair16(a0, a1);
-    });
-
-    // stage C: 16-to-1 through LDS (writer-major rows, odd stride)
-    const int row = lane >> 4, pos = lane & 15;
-    T* rb = red + row * 16 * kRedStride;
+    for (int r = 0; r < RPL; ++r) x[r] = bpermute(src, c[r][SJ]);
+    T sp = x[0] * x[0];
 #pragma unroll
-    for (int t = 0; t < HB; ++t) rb[pos * kRedStride + t] = b[t];
-    wave_sync();
-    T u[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) u[i] = rb[i * kRedStride + pos];
-#pragma unroll
-    for (int h = 8; h >= 1; h >>= 1)
-#pragma unroll
-        for (int i = 0; i < h; ++i) u[i] = u[i] + u[i + h];
-    const T d = u[0];
-    const int vh = 4 * pos + 2 * (row & 1) + (row >> 1);   // value index held by this lane
-
-    // reflector (uniform across the wave)
-    const T sigma2 = readlane(d, 0);
+    for (int r = 1; r < RPL; ++r) sp = __builtin_fma(x[r], x[r], sp);
+    const T sigma2 = row_allreduce16(sp);
     const T alpha = Rs[OFF];
-    T tau = T(0), s = T(0), beta = alpha;
-    if (sigma2 >= Limits<T>::tiny) {
-        const T nrm = __builtin_sqrt(__builtin_fma(alpha, alpha, sigma2));
-        beta = __builtin_signbit(alpha) ? nrm : -nrm;
-        tau = (beta - alpha) / beta;
-        s = T(1) / (alpha - beta);
-    }
-    const T ts = tau * s;
+    const Reflector<T> h = make_reflector(alpha, sigma2);
 
     if constexpr (K > 0) {
-        if (vh >= 1 && vh <= K) {
-            const T rjk = Rs[OFF + vh];
-            const T w = __builtin_fma(s, d, rjk);
-            Rs[OFF + vh] = __builtin_fma(-tau, w, rjk);
-            F[vh - 1] = ts * w;
+        // (b) partial dot products of the live slots (slot SJ is live only in
+        // lane rows q > QJ; elsewhere its result is ignored), one 16 x 17 LDS
+        // tile per lane row: writer p puts slot s at [s][p]
+        T* rq = red + q * 16 * kRedStride;
+        static_for<SJ, NS>([&](auto sc) {
+            constexpr int s = decltype(sc)::value;
+            T acc = x[0] * c[0][s];
+#pragma unroll
+            for (int r = 1; r < RPL; ++r) acc = __builtin_fma(x[r], c[r][s], acc);
+            rq[s * kRedStride + p] = acc;
+        });
+        lds_order();
+        // (c) lane (q, p) completes column k = 4p + q: sum of the 16 writers
+        T u[16];
+        const T* rd = rq + p * kRedStride;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) u[i] = rd[i];
+#pragma unroll
+        for (int hh = 8; hh >= 1; hh >>= 1)
+#pragma unroll
+            for (int i = 0; i < hh; ++i) u[i] = u[i] + u[i + hh];
+        const int k = 4 * p + q;
+        T fv = T(0);
+        if (k > J && k < NC) {
+            const T rjk = Rs[OFF + k - J];
+            const T w = __builtin_fma(h.s, u[0], rjk);
+            Rs[OFF + k - J] = __builtin_fma(-h.tau, w, rjk);
+            fv = h.ts * w;
         }
+        if (p < NS) F[q * 16 + p] = fv;      // zero for finished columns k <= J
     }
-    if (lane == 0) Rs[OFF] = beta;
-    wave_sync();
+    if (q == 0 && p == 0) Rs[OFF] = h.beta;
+    lds_order();
+
     if constexpr (K > 0) {
-        // rank-1 update, reading the K coefficients in groups of kGroup so that
-        // at most two groups are live in registers (reads of group g+1 overlap
-        // the FMAs of group g)
-        constexpr int NG = (K + kGroup - 1) / kGroup;
-        T f[2][kGroup];
-        auto load_group = [&](auto gc, T (&dst)[kGroup]) {
-            constexpr int g = decltype(gc)::value;
+        // (d) rank-1 update of the live slots
+        static_for<SJ, NS>([&](auto sc) {
+            constexpr int s = decltype(sc)::value;
+            const T f = F[q * 16 + s];
 #pragma unroll
-            for (int i = 0; i < kGroup; ++i)
-                if (g * kGroup + i < K) dst[i] = F[g * kGroup + i];
-        };
-        load_group(std::integral_constant<int, 0>{}, f[0]);
-        static_for<0, NG>([&](auto gc) {
-            constexpr int g = decltype(gc)::value;
-            if constexpr (g + 1 < NG) load_group(std::integral_constant<int, g + 1>{}, f[(g + 1) & 1]);
-#pragma unroll
-            for (int i = 0; i < kGroup; ++i) {
-                const int v = 1 + g * kGroup + i;
-                if (v <= K) {
-#pragma unroll
-                    for (int r = 0; r < RPL; ++r)
-                        c[r][J + v] = __builtin_fma(-f[g & 1][i], c[r][J], c[r][J + v]);
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
+            for (int r = 0; r < RPL; ++r) c[r][s] = __builtin_fma(-f, x[r], c[r][s]);
         });
     }
+
+    // (e) the pivot column's registers (lane row QJ, slot SJ)
     if constexpr (M == Mode::Operator) {
         // the Householder vector v = s x replaces x (identity reflector: x kept)
-        if (tau != T(0)) {
+        const bool mine = (q == QJ) && (h.tau != T(0));
 #pragma unroll
-            for (int r = 0; r < RPL; ++r) c[r][J] = s * c[r][J];
-        }
-        if (lane == 0) tau_out[J] = tau;
+        for (int r = 0; r < RPL; ++r) c[r][SJ] = mine ? h.s * x[r] : c[r][SJ];
+        if (q == 0 && p == 0) tau_out[J] = h.tau;
     } else if constexpr (M == Mode::Leaf) {
-        // column J of this chunk is finished: its registers take the next chunk's column J
-        prefetch_column<T, NC, RPL>(c, J, pf, lane);
+        // slot SJ is finished in every lane row: it takes the next chunk's columns
+        if constexpr (QJ == 3 || J == NC - 1) {
+            const bool colok = pf.cols_left > 0;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) c[r][SJ] = (colok && pf.ok[r]) ? pf.col[p + 16 * r] : T(0);
+            pf.col += pf.lda4;
+            pf.cols_left -= 4;
+        }
     }
-    __builtin_amdgcn_sched_barrier(0);
 }
 
 template <typename T, int NC, int RPL, Mode M>
-__device__ __forceinline__ void merge_chunk(T (&c)[RPL][NC], T* Rs, T* red, T* F, int lane,
+__device__ __forceinline__ void merge_chunk(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* red, T* F, int q, int p,
                                             Prefetch<T, RPL>& pf, T* tau_out)
 {
     static_for<0, NC>([&](auto jc) {
-        hh_step<T, NC, RPL, M, decltype(jc)::value>(c, Rs, red, F, lane, pf, tau_out);
+        hh_step<T, NC, RPL, M, decltype(jc)::value>(c, Rs, red, F, q, p, pf, tau_out);
     });
 }
 
 // Load the packed triangle `tri` (NC*(NC+1)/2 values, rows packed; LDS or
-// global) into registers one row per lane: lane i holds R(i, k) for k >= i,
-// zero elsewhere.
-template <typename T, int NC>
-__device__ __forceinline__ void triangle_to_rows(const T* tri, T (&c)[1][NC], int lane)
+// global) into the chunk layout: row i = p + 16r, column k = 4s + q holds
+// R(i, k) for i <= k < NC, zero elsewhere.
+template <typename T, int NC, int RPL>
+__device__ __forceinline__ void triangle_to_slots(const T* tri, T (&c)[RPL][Slots<NC>::NS], int q, int p)
 {
-    const int base = (lane < NC) ? Tri<NC>::off(lane) - lane : 0;
+    constexpr int NS = Slots<NC>::NS;
 #pragma unroll
-    for (int k = 0; k < NC; ++k) c[0][k] = (lane < NC && k >= lane) ? tri[base + k] : T(0);
+    for (int r = 0; r < RPL; ++r) {
+        const int i = p + 16 * r;
+        const int base = (i < NC) ? Tri<NC>::off(i) - i : 0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int k = 4 * s + q;
+            c[r][s] = (i < NC && k < NC && k >= i) ? tri[base + k] : T(0);
+        }
+    }
 }
 
 // ---- the fused leaf + tree kernel --------------------------------------------
 
 template <typename T, int NC, int RPL>
-__global__ void __launch_bounds__(kWave) tsqr_leaf_tree_kernel(LeafTreeArgs<T> p)
+__global__ void __launch_bounds__(kWave) tsqr_leaf_tree_kernel(LeafTreeArgs<T> a)
 {
-    constexpr int CH = kWave * RPL;
+    constexpr int CH = 16 * RPL;                  // rows per chunk
     constexpr int NT = Tri<NC>::kSize;
+    constexpr int NS = Slots<NC>::NS;
+    constexpr int RPLM = (NC + 15) / 16;          // rows per lane of a merged triangle
     __shared__ T Rs[NT];
     __shared__ T red[kRedElems];
     __shared__ T F[kWave];
     const int lane = threadIdx.x;
+    const int q = lane >> 4, p = lane & 15;
     const int leaf = blockIdx.x;
-    const int64_t r0 = (int64_t)leaf * p.leaf_rows;
-    const int64_t r1 = (r0 + p.leaf_rows < p.m) ? r0 + p.leaf_rows : p.m;
+    const int64_t r0 = (int64_t)leaf * a.leaf_rows;
+    const int64_t r1 = (r0 + a.leaf_rows < a.m) ? r0 + a.leaf_rows : a.m;
 
     for (int i = lane; i < NT; i += kWave) Rs[i] = T(0);
 
     // step 1 of the method: the local factorisation of rows [r0, r1)
     if (r1 > r0) {
-        T c[RPL][NC];
+        T c[RPL][NS];
         {
-            Prefetch<T, RPL> first = make_prefetch<T, RPL>(p.A, p.lda, p.n, r0, r1, lane);
 #pragma unroll
-            for (int j = 0; j < NC; ++j) prefetch_column<T, NC, RPL>(c, j, first, lane);
+            for (int r = 0; r < RPL; ++r) {
+                const int64_t row = r0 + p + 16 * r;
+                const bool ok = row < r1;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const int k = 4 * s + q;
+                    c[r][s] = (ok && k < a.n) ? a.A[row + (int64_t)k * a.lda] : T(0);
+                }
+            }
         }
         wave_sync();
         const int64_t nchunks = (r1 - r0 + CH - 1) / CH;
         for (int64_t t = 0; t < nchunks; ++t) {
-            Prefetch<T, RPL> pf = make_prefetch<T, RPL>(p.A, p.lda, p.n, r0 + (t + 1) * CH, r1, lane);
-            merge_chunk<T, NC, RPL, Mode::Leaf>(c, Rs, red, F, lane, pf, nullptr);
+            Prefetch<T, RPL> pf = make_prefetch<T, RPL>(a.A, a.lda, a.n, r0 + (t + 1) * CH, r1, q, p);
+            merge_chunk<T, NC, RPL, Mode::Leaf>(c, Rs, red, F, q, p, pf, nullptr);
         }
     }
     wave_sync();
 
     // step 2: binary reduction tree across leaves
-    const int P = p.leaves;
+    const int P = a.leaves;
     int node = leaf;
     int level = 0;
     bool root = (P == 1);
     if (!root) {
-        T* slot = p.tri + (int64_t)node * NT;
+        T* slot = a.tri + (int64_t)node * NT;
         for (int i = lane; i < NT; i += kWave) slot[i] = Rs[i];
     }
     while (!root) {
@@ -361,38 +388,38 @@ __global__ void __launch_bounds__(kWave) tsqr_leaf_tree_kernel(LeafTreeArgs<T> p
         const int id = left + span - 1;         // distinct for every (level, left) pair
         __threadfence();
         unsigned old = 0;
-        if (lane == 0) old = atomicAdd(&p.tickets[id], 1u);
+        if (lane == 0) old = atomicAdd(&a.tickets[id], 1u);
         old = (unsigned)__builtin_amdgcn_readfirstlane((int)old);
         if (old == 0) return;                   // the partner will merge
         __threadfence();
-        if (lane == 0) p.tickets[id] = 0u;      // both arrived: reset for the next call
+        if (lane == 0) a.tickets[id] = 0u;      // both arrived: reset for the next call
 
-        T c1[1][NC];
+        T c1[RPLM][NS];
         if (is_left) {
-            triangle_to_rows<T, NC>(p.tri + (int64_t)partner * NT, c1, lane);
+            triangle_to_slots<T, NC, RPLM>(a.tri + (int64_t)partner * NT, c1, q, p);
         } else {
             // this wavefront holds the right (lower) operand: move it to registers
             // and bring the left one into LDS, keeping the lower index on top
-            triangle_to_rows<T, NC>(Rs, c1, lane);
+            triangle_to_slots<T, NC, RPLM>(Rs, c1, q, p);
             wave_sync();
-            const T* lt = p.tri + (int64_t)partner * NT;
+            const T* lt = a.tri + (int64_t)partner * NT;
             for (int i = lane; i < NT; i += kWave) Rs[i] = lt[i];
         }
         wave_sync();
-        Prefetch<T, 1> none{};
-        merge_chunk<T, NC, 1, Mode::Merge>(c1, Rs, red, F, lane, none, nullptr);
+        Prefetch<T, RPLM> none{};
+        merge_chunk<T, NC, RPLM, Mode::Merge>(c1, Rs, red, F, q, p, none, nullptr);
         wave_sync();
         node = left;
         ++level;
         root = ((1 << level) >= P);
         if (!root) {
-            T* slot = p.tri + (int64_t)node * NT;
+            T* slot = a.tri + (int64_t)node * NT;
             for (int i = lane; i < NT; i += kWave) slot[i] = Rs[i];
         }
     }
 
     // root: positive diagonal, +0 below it, leading n-by-n block only
-    const int n = p.n;
+    const int n = a.n;
     for (int idx = lane; idx < n * n; idx += kWave) {
         const int i = idx % n, k = idx / n;
         T v = T(0);
@@ -400,7 +427,7 @@ __global__ void __launch_bounds__(kWave) tsqr_leaf_tree_kernel(LeafTreeArgs<T> p
             v = Rs[Tri<NC>::off(i) + (k - i)];
             if (__builtin_signbit(Rs[Tri<NC>::off(i)])) v = -v;
         }
-        p.R[i + (int64_t)k * p.ldr] = v;
+        a.R[i + (int64_t)k * a.ldr] = v;
     }
 }
 
@@ -410,11 +437,14 @@ template <typename T, int NC>
 __global__ void __launch_bounds__(kWave) qr_uppers_kernel(int n, T* R1, T* R2, T* tau)
 {
     constexpr int NT = Tri<NC>::kSize;
+    constexpr int NS = Slots<NC>::NS;
+    constexpr int RPLM = (NC + 15) / 16;
     __shared__ T Rs[NT];
     __shared__ T red[kRedElems];
     __shared__ T F[kWave];
     __shared__ T taus[NC];
     const int lane = threadIdx.x;
+    const int q = lane >> 4, p = lane & 15;
     for (int idx = lane; idx < NT; idx += kWave) {
         // packed index -> (row, column)
         int i = 0;
@@ -422,20 +452,33 @@ __global__ void __launch_bounds__(kWave) qr_uppers_kernel(int n, T* R1, T* R2, T
         const int k = i + (idx - Tri<NC>::off(i));
         Rs[idx] = (i < n && k < n) ? R1[i + (int64_t)k * n] : T(0);
     }
-    T c[1][NC];
+    T c[RPLM][NS];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) c[0][k] = (lane < n && k < n && k >= lane) ? R2[lane + (int64_t)k * n] : T(0);
+    for (int r = 0; r < RPLM; ++r) {
+        const int i = p + 16 * r;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int k = 4 * s + q;
+            c[r][s] = (i < n && k < n && k >= i) ? R2[i + (int64_t)k * n] : T(0);
+        }
+    }
     wave_sync();
-    Prefetch<T, 1> none{};
-    merge_chunk<T, NC, 1, Mode::Operator>(c, Rs, red, F, lane, none, taus);
+    Prefetch<T, RPLM> none{};
+    merge_chunk<T, NC, RPLM, Mode::Operator>(c, Rs, red, F, q, p, none, taus);
     wave_sync();
     for (int idx = lane; idx < n * n; idx += kWave) {
         const int i = idx % n, k = idx / n;
         if (k >= i) R1[idx] = Rs[Tri<NC>::off(i) + (k - i)];
     }
 #pragma unroll
-    for (int k = 0; k < NC; ++k)
-        if (lane < n && k < n && k >= lane) R2[lane + (int64_t)k * n] = c[0][k];
+    for (int r = 0; r < RPLM; ++r) {
+        const int i = p + 16 * r;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int k = 4 * s + q;
+            if (i < n && k < n && k >= i) R2[i + (int64_t)k * n] = c[r][s];
+        }
+    }
     if (lane < n) tau[lane] = taus[lane];
 }
 

@@ -30,17 +30,19 @@ hipError_t TSQR_OP_FN2(TSQR_INST_TAG, TSQR_INST_NC)(int n, TSQR_INST_TAG* R1, TS
 }
 #elif defined(TSQR_INST_COMMON)
 namespace dev {
-__global__ void zero_u32_kernel(unsigned* p, int count)
+__global__ void zero_u32_kernel(unsigned* p, int64_t count)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = 0u;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0u;
 }
 }  // namespace dev
 
-hipError_t launch_zero_u32(unsigned* p, int count, hipStream_t s)
+hipError_t launch_zero_u32(unsigned* p, int64_t count, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(dev::zero_u32_kernel, dim3((count + 255) / 256), dim3(256), 0, s, p, count);
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(dev::zero_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, count);
     return hipGetLastError();
 }
 #else

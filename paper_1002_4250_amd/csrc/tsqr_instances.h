@@ -1,13 +1,13 @@
 // tsqr_instances.h -- the kernel instantiations compiled into libtsqr.so.
 // Each X(tag, NC, RPL) is a leaf+tree kernel for element type tag (f64/f32),
-// NC compiled columns and RPL rows per lane; each O(tag, NC) an operator
+// NC compiled columns and RPL rows per lane (a chunk is 16*RPL rows); each O(tag, NC) an operator
 // kernel.  The build compiles one translation unit per entry (in parallel) and
 // the C-ABI layer dispatches through the same lists.
 #pragma once
 
 #define TSQR_LEAF_INSTANCES(X) \
-    X(f64, 16, 2) X(f64, 32, 2) X(f64, 50, 1) X(f64, 50, 2) X(f64, 50, 3) X(f64, 64, 2) \
-    X(f32, 16, 4) X(f32, 32, 4) X(f32, 50, 2) X(f32, 50, 4) X(f32, 64, 4)
+    X(f64, 16, 8) X(f64, 32, 8) X(f64, 50, 4) X(f64, 50, 6) X(f64, 50, 8) X(f64, 64, 8) \
+    X(f32, 16, 16) X(f32, 32, 16) X(f32, 50, 8) X(f32, 50, 12) X(f32, 50, 16) X(f32, 64, 16)
 
 #define TSQR_OP_INSTANCES(O) \
     O(f64, 16) O(f64, 32) O(f64, 50) O(f64, 64) \
@@ -15,5 +15,5 @@
 
 // column counts with a compiled kernel (ascending) and the default rows per lane
 #define TSQR_NC_VALUES 16, 32, 50, 64
-#define TSQR_DEFAULT_RPL_F64 2
-#define TSQR_DEFAULT_RPL_F32 4
+#define TSQR_DEFAULT_RPL_F64 8
+#define TSQR_DEFAULT_RPL_F32 8

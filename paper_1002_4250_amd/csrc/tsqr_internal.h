@@ -18,7 +18,7 @@ struct LeafTreeArgs {
     int64_t leaf_rows;    // rows per leaf (multiple of the chunk)
     int leaves;           // P = ceil(m / leaf_rows), at least 1
     T* tri;               // workspace: P packed triangles
-    unsigned* tickets;    // workspace: P tree counters (zeroed by the launcher)
+    unsigned* tickets;    // workspace: P tree counters, zero on entry and on exit
     T* R;                 // n-by-n output
     int64_t ldr;
 };
@@ -35,6 +35,6 @@ TSQR_OP_INSTANCES(TSQR_DECLARE_OP)
 #undef TSQR_DECLARE_LEAF
 #undef TSQR_DECLARE_OP
 
-hipError_t launch_zero_u32(unsigned* p, int count, hipStream_t s);
+hipError_t launch_zero_u32(unsigned* p, int64_t count, hipStream_t s);
 
 }  // namespace tsqr

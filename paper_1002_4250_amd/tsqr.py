@@ -169,13 +169,14 @@ def _col_major(A):
 
 
 def workspace(m: int, n: int, dtype, device=None, h=None):
-    """A uint8 workspace tensor large enough for geqr_r(m, n)."""
+    """A uint8 workspace tensor large enough for geqr_r(m, n) with the
+    handle's current options."""
     import torch
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     h = h or handle(dev.index or 0)
     code = TSQR_F64 if dtype == torch.float64 else TSQR_F32
-    nbytes = tsqr_workspace_bytes(h, m, n, code)
-    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+    nbytes = max(tsqr_workspace_bytes(h, m, n, code), 256)
+    return torch.empty(nbytes, dtype=torch.uint8, device=dev)
 
 
 def geqr_r(A, R=None, ws=None, h=None):

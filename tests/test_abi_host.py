@@ -92,13 +92,13 @@ def test_plan_geometry(ph):
     lr, P = tsqr.tsqr_plan_info(ph, 1 << 22, 50, tsqr.TSQR_F64)
     assert lr * P >= 1 << 22 and lr * (P - 1) < 1 << 22
     assert 256 * 2 <= P <= 256 * 8
-    chunk = 64 * 2
+    chunk = 16 * 8
     assert lr % chunk == 0
     ws = tsqr.tsqr_workspace_bytes(ph, 1 << 22, 50, tsqr.TSQR_F64)
     assert ws >= P * 4 + P * (50 * 51 // 2) * 8 and ws % 256 == 0
     # tiny m: one leaf of one chunk
     lr, P = tsqr.tsqr_plan_info(ph, 1, 3, tsqr.TSQR_F32)
-    assert P == 1 and lr == 64 * 4
+    assert P == 1 and lr == 16 * 8
     # forced leaf size, rounded up to a chunk
     tsqr.tsqr_set_option(ph, tsqr.TSQR_OPT_LEAF_ROWS, 100)
     lr, P = tsqr.tsqr_plan_info(ph, 1000, 50, tsqr.TSQR_F64)

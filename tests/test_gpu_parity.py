@@ -117,8 +117,8 @@ def test_config1_small_instance():
     Ro = oracle.r_factor(A)
     assert relF(gpu_r(A), Ro) < TOL64
     # the 4-leaf binary tree of the paper's figure (four blocks of 64 rows)
-    assert relF(gpu_r(A, leaf_rows=64, rpl=1), Ro) < TOL64
-    assert relF(gpu_r(A, leaf_rows=64, rpl=1), oracle.tsqr_r(A, 64, "binary")) < TOL64
+    assert relF(gpu_r(A, leaf_rows=64, rpl=4), Ro) < TOL64
+    assert relF(gpu_r(A, leaf_rows=64, rpl=4), oracle.tsqr_r(A, 64, "binary")) < TOL64
 
 
 @pytest.mark.parametrize("m,n", [(1, 1), (1, 50), (2, 2), (5, 3), (49, 50), (50, 50), (51, 50), (63, 17),
@@ -142,7 +142,7 @@ def test_deep_tree_many_leaves():
     assert relF(gpu_r(A, leaf_rows=128), oracle.r_factor(A)) < TOL64
 
 
-@pytest.mark.parametrize("rpl", [1, 2, 3])
+@pytest.mark.parametrize("rpl", [4, 6, 8])
 def test_rows_per_lane_variants(rpl):
     A = inputs.uniform(5000, 50, 33)
     assert relF(gpu_r(A, rpl=rpl), oracle.r_factor(A)) < TOL64
@@ -168,6 +168,20 @@ def test_bitwise_reproducible():
     A = inputs.uniform(50000, 50, 36)
     R1, R2 = gpu_r(A), gpu_r(A)
     assert np.array_equal(R1, R2)
+
+
+def test_workspace_reused_across_calls_and_sizes():
+    """One workspace serves calls of different sizes: a call with fewer
+    leaves writes triangles where a later call with more leaves keeps its tree
+    counters, so every call must start from zeroed counters."""
+    h = tsqr.handle(0)
+    ws = tsqr.workspace(200000, 50, torch.float64)
+    for m in (200000, 777, 65536, 200000, 5):
+        A = inputs.uniform(m, 50, 60 + m)
+        Ad = to_dev(A)
+        R = tsqr.geqr_r(Ad, ws=ws)
+        torch.cuda.synchronize()
+        assert relF(R.cpu().numpy(), oracle.r_factor(A)) < TOL64
 
 
 def test_power_of_two_scaling_bitexact():
@@ -209,7 +223,7 @@ def test_argument_errors_with_device():
     A = torch.zeros((100, 5), dtype=torch.float64, device="cuda").t().contiguous().t()
     R = torch.zeros((5, 5), dtype=torch.float64, device="cuda")
     need = tsqr.tsqr_workspace_bytes(h, 100, 5, tsqr.TSQR_F64)
-    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    ws = tsqr.workspace(100, 5, torch.float64)
     L = tsqr.lib()
     assert L.tsqr_geqr_r_f64(h, 100, 5, A.data_ptr(), 99, R.data_ptr(), 5, ws.data_ptr(), need, None) == -5
     assert L.tsqr_geqr_r_f64(h, 100, 5, A.data_ptr(), 100, R.data_ptr(), 5, ws.data_ptr(), need - 8, None) == -9
