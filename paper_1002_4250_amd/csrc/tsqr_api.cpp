@@ -64,9 +64,16 @@ int plan(const tsqr_handle_s* h, int64_t m, int64_t n, int dtype, Geometry* g)
     if (g->nc < 0) return TSQR_ERR_UNSUPPORTED;
     g->rpl = (int)(h->rpl > 0 ? h->rpl : (dtype == TSQR_F64 ? TSQR_DEFAULT_RPL_F64 : TSQR_DEFAULT_RPL_F32));
     if (!leaf_instance_exists(dtype, g->nc, g->rpl)) {
-        // fall back to the default rows-per-lane for this column count
+        // fall back to the default rows-per-lane, else any compiled one, for this column count
         g->rpl = dtype == TSQR_F64 ? TSQR_DEFAULT_RPL_F64 : TSQR_DEFAULT_RPL_F32;
-        if (!leaf_instance_exists(dtype, g->nc, g->rpl)) return TSQR_ERR_UNSUPPORTED;
+        if (!leaf_instance_exists(dtype, g->nc, g->rpl)) {
+            g->rpl = 0;
+#define TSQR_ANY(tag, NC, RPL) \
+    if (g->rpl == 0 && (dtype == TSQR_F64) == (sizeof(tsqr::tag) == 8) && g->nc == NC) g->rpl = RPL;
+            TSQR_LEAF_INSTANCES(TSQR_ANY)
+#undef TSQR_ANY
+            if (g->rpl == 0) return TSQR_ERR_UNSUPPORTED;
+        }
     }
     const int64_t chunk = (int64_t)kRowsPerLaneUnit * g->rpl;
     int64_t L;

@@ -7,7 +7,7 @@
 
 #define TSQR_LEAF_INSTANCES(X) \
     X(f64, 16, 8) X(f64, 32, 8) X(f64, 50, 4) X(f64, 50, 6) X(f64, 50, 8) X(f64, 64, 8) \
-    X(f32, 16, 16) X(f32, 32, 16) X(f32, 50, 8) X(f32, 50, 12) X(f32, 50, 16) X(f32, 64, 16)
+    X(f32, 16, 8) X(f32, 32, 8) X(f32, 50, 8) X(f32, 50, 12) X(f32, 50, 16) X(f32, 64, 8)
 
 #define TSQR_OP_INSTANCES(O) \
     O(f64, 16) O(f64, 32) O(f64, 50) O(f64, 64) \
