@@ -37,6 +37,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tsqr_leaf_tree_f64_m4194304_n50_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the leaf+tree kernel from the committed counter
+    runs (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy), or None if
+    the kernel sources changed since those counters were taken."""
+    try:
+        from paper_1002_4250_amd import build as b
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        if rec.get("kernel_source_digest") != b._digest(b.KERNEL_DEPS):
+            return None
+        return rec["hbm_bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        return None
+
+
 def to_device_colmajor(torch, A):
     import numpy as np
     return torch.from_numpy(np.ascontiguousarray(A.T)).to("cuda").t()
@@ -76,6 +94,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--m", type=int, default=1 << 22)
     ap.add_argument("--n", type=int, default=50)
+    ap.add_argument("--profile-copy-bytes", type=int, default=0,
+                    help="after timing, run one plain device-to-device copy of this many bytes (the "
+                         "reference kernel that calibrates the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build runs on a single MI355X); --gpus {args.gpus} "
@@ -131,6 +152,14 @@ def main():
         acc32 = float(np.linalg.norm(R32 - Ro32) / np.linalg.norm(Ro32))
         log(f"accuracy vs oracle: fp64 {acc64:.2e}, fp32 {acc32:.2e}")
 
+    if args.profile_copy_bytes > 0:
+        src = torch.empty(args.profile_copy_bytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    traffic = measured_traffic()
     out = {
         "metric": METRIC,
         "value": 1000.0 / ms_step,
@@ -147,7 +176,7 @@ def main():
         "config": {"workload": f"tsqr_r_factor m={m} n={n} fp64 uniform[-1,1) seed 1, one instance per step",
                    "m": m, "n": n, "leaves": leaves, "leaf_rows": leaf_rows, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": tflops / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": tflops / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "kernel": "tsqr_leaf_tree_kernel<double,50>", "kernel_ms": ms_kernel,
                      "hbm_GBs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS},
         "cpu_baseline": cpu,
