@@ -140,6 +140,44 @@ int tsqr_qr_uppers_f64(tsqr_handle_t handle, int64_t n, double *R1, double *R2, 
 int tsqr_qr_uppers_f32(tsqr_handle_t handle, int64_t n, float *R1, float *R2, float *tau,
                        void *stream);
 
+/* ---- many independent matrices in one launch ------------------------------
+ *
+ * A batch of `batch` matrices with the same column count n and individual row
+ * counts m[b] (any mix of sizes, e.g. 64 to 65536 rows).  Every instance gets
+ * the method of section 2 (local QR of its row blocks, then its own binary
+ * tree of qr_uppers merges); the (instance, block) tiles of all instances run
+ * in ONE kernel launch, longest blocks first, so the trees of some instances
+ * overlap the block factorisations of others.  A plan holds the tile schedule
+ * on the device; executing it allocates nothing and is safe to capture in a
+ * HIP graph (its two launches are kernels, no memset).
+ *
+ * Create: m, a_offset, lda are HOST arrays of `batch` entries: instance b is
+ * the m[b]-by-n column-major matrix at element offset a_offset[b] of the A
+ * pointer given to tsqr_batch_exec, with leading dimension lda[b] (NULL:
+ * lda[b] = max(1, m[b])).  The leaf size is the handle's TSQR_OPT_LEAF_ROWS if
+ * set, else 32 chunks.  The plan allocates two small device tables (freed by
+ * tsqr_batch_plan_destroy) and keeps a pointer to the handle, which must
+ * outlive it.  Argument codes: -1 handle, -2 batch, -3 n, -4 m, -5 a_offset,
+ * -6 lda, -7 dtype, -8 plan. */
+int tsqr_batch_plan_create(tsqr_handle_t handle, int64_t batch, int64_t n, const int64_t *m,
+                           const int64_t *a_offset, const int64_t *lda, int dtype,
+                           tsqr_batch_plan_t *plan);
+int tsqr_batch_plan_destroy(tsqr_batch_plan_t plan);
+
+/* Workspace bytes for tsqr_batch_exec (tree counters and triangles of all
+ * instances), or -1 for a NULL plan. */
+int64_t tsqr_batch_workspace_bytes(tsqr_batch_plan_t plan);
+
+/* Tiles (workgroups), leaves over all instances and rows per leaf. */
+int tsqr_batch_plan_info(tsqr_batch_plan_t plan, int64_t *tiles, int64_t *leaves, int64_t *leaf_rows);
+
+/* R of every instance: instance b's n-by-n R (diag >= 0, column-major,
+ * leading dimension ldr >= n) is written at R + b*ldr*n elements.  A and R
+ * are device pointers of the plan's element type; ws as for tsqr_geqr_r_*.
+ * Argument codes: -1 plan, -2 A, -3 R, -4 ldr, -5 ws, -6 ws_bytes. */
+int tsqr_batch_exec(tsqr_batch_plan_t plan, const void *A, void *R, int64_t ldr, void *ws, int64_t ws_bytes,
+                    void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,8 +5,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <new>
 #include <string.h>
+#include <vector>
 
 #include "tsqr_internal.h"
 
@@ -108,6 +110,20 @@ hipError_t dispatch_leaf(const tsqr::LeafTreeArgs<T>& a, int nc, int rpl, hipStr
         if (nc == NC && rpl == RPL)                                                     \
             return tsqr::launch_leaf_tree_##tag##_##NC##_##RPL(                         \
                 reinterpret_cast<const tsqr::LeafTreeArgs<tsqr::tag>&>(a), s);          \
+    }
+    TSQR_LEAF_INSTANCES(TSQR_CALL)
+#undef TSQR_CALL
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t dispatch_batch(const tsqr::BatchArgs<T>& a, int tiles, int nc, int rpl, hipStream_t s)
+{
+#define TSQR_CALL(tag, NC, RPL)                                                         \
+    if constexpr (sizeof(T) == sizeof(tsqr::tag)) {                                     \
+        if (nc == NC && rpl == RPL)                                                     \
+            return tsqr::launch_batch_##tag##_##NC##_##RPL(                             \
+                reinterpret_cast<const tsqr::BatchArgs<tsqr::tag>&>(a), tiles, s);      \
     }
     TSQR_LEAF_INSTANCES(TSQR_CALL)
 #undef TSQR_CALL
@@ -309,6 +325,179 @@ int tsqr_qr_uppers_f64(tsqr_handle_t handle, int64_t n, double* R1, double* R2, 
 int tsqr_qr_uppers_f32(tsqr_handle_t handle, int64_t n, float* R1, float* R2, float* tau, void* stream)
 {
     return qr_uppers<float>(handle, n, R1, R2, tau, stream);
+}
+
+// ---- batched --------------------------------------------------------------
+
+struct tsqr_batch_plan_s {
+    tsqr_handle_s* h;
+    int dtype;
+    int64_t batch;
+    int64_t n;
+    int nc;
+    int rpl;
+    int64_t leaf_rows;
+    int64_t leaves;          // all instances
+    int64_t tiles;
+    int64_t ticket_bytes;
+    int64_t ws_bytes;
+    tsqr::BatchInstance* d_inst;
+    tsqr::BatchTile* d_tiles;
+};
+
+int tsqr_batch_plan_create(tsqr_handle_t h, int64_t batch, int64_t n, const int64_t* m, const int64_t* a_offset,
+                           const int64_t* lda, int dtype, tsqr_batch_plan_t* out)
+{
+    if (!h) return -1;
+    if (batch < 0) return -2;
+    if (n < 0) return -3;
+    if (batch > 0 && !m) return -4;
+    if (batch > 0 && !a_offset) return -5;
+    if (dtype != TSQR_F64 && dtype != TSQR_F32) return -7;
+    if (!out) return -8;
+    *out = nullptr;
+    for (int64_t b = 0; b < batch; ++b) {
+        if (m[b] < 0) return -4;
+        if (a_offset[b] < 0) return -5;
+        const int64_t ld = lda ? lda[b] : (m[b] > 1 ? m[b] : 1);
+        if (ld < (m[b] > 1 ? m[b] : 1)) return -6;
+    }
+    if (n > TSQR_MAX_N) return TSQR_ERR_UNSUPPORTED;
+    Geometry g;
+    int rc = n > 0 ? plan(h, 1, n, dtype, &g) : 0;
+    if (rc) return rc;
+    const int64_t chunk = (int64_t)kRowsPerLaneUnit * (n > 0 ? g.rpl : 1);
+    // batched leaves: the handle's leaf size if set, else 32 chunks (long
+    // enough that streaming dominates, short enough to split big instances)
+    const int64_t L = h->leaf_rows > 0 ? align_up(h->leaf_rows, chunk) : 32 * chunk;
+    std::vector<tsqr::BatchInstance> inst((size_t)batch);
+    std::vector<tsqr::BatchTile> tiles;
+    std::vector<int64_t> tile_rows;
+    int64_t leaves = 0;
+    for (int64_t b = 0; b < batch; ++b) {
+        tsqr::BatchInstance& in = inst[(size_t)b];
+        in.a_off = a_offset[b];
+        in.m = m[b];
+        in.lda = lda ? lda[b] : (m[b] > 1 ? m[b] : 1);
+        in.leaf_rows = L;
+        const int64_t P = m[b] > 0 ? (m[b] + L - 1) / L : 1;
+        if (P > ((int64_t)1 << 30)) return TSQR_ERR_UNSUPPORTED;
+        in.leaves = (int32_t)P;
+        in.pad = 0;
+        in.ticket_off = leaves;
+        in.tri_off = leaves * (n > 0 ? g.tri_elems : 0);
+        for (int64_t i = 0; i < P; ++i) {
+            tiles.push_back(tsqr::BatchTile{(int32_t)b, (int32_t)i});
+            const int64_t r = std::min(L, m[b] - i * L);
+            tile_rows.push_back(r > 0 ? r : 0);
+        }
+        leaves += P;
+    }
+    if (batch > ((int64_t)1 << 31) - 1 || (int64_t)tiles.size() > ((int64_t)1 << 31) - 1) return TSQR_ERR_UNSUPPORTED;
+    // longest tiles first (stable: equal lengths keep instance order)
+    std::vector<int64_t> order(tiles.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int64_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return tile_rows[(size_t)x] > tile_rows[(size_t)y]; });
+    std::vector<tsqr::BatchTile> sorted(tiles.size());
+    for (size_t i = 0; i < order.size(); ++i) sorted[i] = tiles[(size_t)order[i]];
+
+    tsqr_batch_plan_s* p = new (std::nothrow) tsqr_batch_plan_s;
+    if (!p) return TSQR_ERR_ALLOC;
+    p->h = h;
+    p->dtype = dtype;
+    p->batch = batch;
+    p->n = n;
+    p->nc = n > 0 ? g.nc : 0;
+    p->rpl = n > 0 ? g.rpl : 0;
+    p->leaf_rows = L;
+    p->leaves = leaves;
+    p->tiles = (int64_t)sorted.size();
+    p->ticket_bytes = align_up(leaves * 4, kAlign);
+    p->ws_bytes = p->ticket_bytes + align_up(leaves * (n > 0 ? g.tri_elems : 0) * elem_bytes(dtype), kAlign);
+    p->d_inst = nullptr;
+    p->d_tiles = nullptr;
+    if (!h->planning_only && batch > 0 && n > 0) {
+        hipError_t e = hipMalloc(&p->d_inst, sizeof(tsqr::BatchInstance) * inst.size());
+        if (e == hipSuccess) e = hipMalloc(&p->d_tiles, sizeof(tsqr::BatchTile) * sorted.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_inst, inst.data(), sizeof(tsqr::BatchInstance) * inst.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_tiles, sorted.data(), sizeof(tsqr::BatchTile) * sorted.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            if (p->d_inst) (void)hipFree(p->d_inst);
+            if (p->d_tiles) (void)hipFree(p->d_tiles);
+            delete p;
+            h->last_hip_error = (int)e;
+            return TSQR_ERR_ALLOC;
+        }
+    }
+    *out = p;
+    return 0;
+}
+
+int tsqr_batch_plan_destroy(tsqr_batch_plan_t plan)
+{
+    if (!plan) return 0;
+    if (plan->d_inst) (void)hipFree(plan->d_inst);
+    if (plan->d_tiles) (void)hipFree(plan->d_tiles);
+    delete plan;
+    return 0;
+}
+
+int64_t tsqr_batch_workspace_bytes(tsqr_batch_plan_t plan)
+{
+    if (!plan) return -1;
+    return plan->ws_bytes;
+}
+
+int tsqr_batch_plan_info(tsqr_batch_plan_t plan, int64_t* tiles, int64_t* leaves, int64_t* leaf_rows)
+{
+    if (!plan) return -1;
+    if (tiles) *tiles = plan->tiles;
+    if (leaves) *leaves = plan->leaves;
+    if (leaf_rows) *leaf_rows = plan->leaf_rows;
+    return 0;
+}
+
+int tsqr_batch_exec(tsqr_batch_plan_t plan, const void* A, void* R, int64_t ldr, void* ws, int64_t ws_bytes,
+                    void* stream)
+{
+    if (!plan) return -1;
+    if (plan->batch > 0 && plan->n > 0 && !A) return -2;
+    if (plan->batch > 0 && plan->n > 0 && !R) return -3;
+    if (ldr < (plan->n > 1 ? plan->n : 1)) return -4;
+    if (plan->batch == 0 || plan->n == 0) return 0;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) != 0) return -5;
+    if (ws_bytes < plan->ws_bytes) return -6;
+    if (plan->h->planning_only) return TSQR_ERR_NO_DEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned* tickets = static_cast<unsigned*>(ws);
+    hipError_t e = tsqr::launch_zero_u32(tickets, plan->leaves, s);
+    if (e != hipSuccess) return hip_status(plan->h, e);
+    if (plan->dtype == TSQR_F64) {
+        tsqr::BatchArgs<double> a;
+        a.A = static_cast<const double*>(A);
+        a.n = (int)plan->n;
+        a.inst = plan->d_inst;
+        a.tiles = plan->d_tiles;
+        a.tri = reinterpret_cast<double*>(static_cast<char*>(ws) + plan->ticket_bytes);
+        a.tickets = tickets;
+        a.R = static_cast<double*>(R);
+        a.ldr = ldr;
+        e = dispatch_batch<double>(a, (int)plan->tiles, plan->nc, plan->rpl, s);
+    } else {
+        tsqr::BatchArgs<float> a;
+        a.A = static_cast<const float*>(A);
+        a.n = (int)plan->n;
+        a.inst = plan->d_inst;
+        a.tiles = plan->d_tiles;
+        a.tri = reinterpret_cast<float*>(static_cast<char*>(ws) + plan->ticket_bytes);
+        a.tickets = tickets;
+        a.R = static_cast<float*>(R);
+        a.ldr = ldr;
+        e = dispatch_batch<float>(a, (int)plan->tiles, plan->nc, plan->rpl, s);
+    }
+    return hip_status(plan->h, e);
 }
 
 }  // extern "C"

@@ -78,17 +78,18 @@ template <> struct Limits<float> { static constexpr float tiny = 1.17549435e-38f
 
 // ---- cross-lane primitives -------------------------------------------------
 
+// Row rotations read a valid lane in every row, so no "old" value is needed.
 template <int CTRL>
 __device__ __forceinline__ double dpp_mov(double x)
 {
-    int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
-    int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+    int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, true);
+    int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float x)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
 }
 
 // Sum over the 16 lanes of each lane row, returned in all 16 (bit-identical).
@@ -211,7 +212,7 @@ __device__ __forceinline__ Prefetch<T, RPL> make_prefetch(const T* A, int64_t ld
 // static and the scheduler can overlap consecutive steps.
 template <typename T, int NC, int RPL, Mode M, int J>
 __device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* red, T* F, int q, int p,
-                                        Prefetch<T, RPL>& pf, T* tau_out)
+                                        int kcol, int spare, Prefetch<T, RPL>& pf, T* tau_out)
 {
     constexpr int NS = Slots<NC>::NS;
     constexpr int QJ = J % 4, SJ = J / 4;     // lane row and slot holding column J
@@ -252,15 +253,15 @@ __device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* re
         for (int hh = 8; hh >= 1; hh >>= 1)
 #pragma unroll
             for (int i = 0; i < hh; ++i) u[i] = u[i] + u[i + hh];
-        const int k = 4 * p + q;
-        T fv = T(0);
-        if (k > J && k < NC) {
-            const T rjk = Rs[OFF + k - J];
-            const T w = __builtin_fma(h.s, u[0], rjk);
-            Rs[OFF + k - J] = __builtin_fma(-h.tau, w, rjk);
-            fv = h.ts * w;
-        }
-        if (p < NS) F[q * 16 + p] = fv;      // zero for finished columns k <= J
+        // branch-free: lanes that own no trailing column read and write a spare
+        // LDS cell and publish a zero coefficient
+        const int k = kcol;
+        const bool own = (k > J) && (k < NC);
+        const int ridx = own ? OFF + k - J : spare;
+        const T rjk = Rs[ridx];
+        const T w = __builtin_fma(h.s, u[0], rjk);
+        Rs[ridx] = __builtin_fma(-h.tau, w, rjk);
+        F[q * 16 + p] = own ? h.ts * w : T(0);
     }
     if (q == 0 && p == 0) Rs[OFF] = h.beta;
     lds_order();
@@ -298,8 +299,14 @@ template <typename T, int NC, int RPL, Mode M>
 __device__ __forceinline__ void merge_chunk(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* red, T* F, int q, int p,
                                             Prefetch<T, RPL>& pf, T* tau_out)
 {
+    // the column a lane completes in the reduction, passed through an opaque
+    // copy so the compiler does not precompute (and keep live) one
+    // ownership predicate per step
+    int kcol = 4 * p + q;
+    asm volatile("" : "+v"(kcol));
+    const int spare = Tri<NC>::kSize;      // one LDS cell past the triangle
     static_for<0, NC>([&](auto jc) {
-        hh_step<T, NC, RPL, M, decltype(jc)::value>(c, Rs, red, F, q, p, pf, tau_out);
+        hh_step<T, NC, RPL, M, decltype(jc)::value>(c, Rs, red, F, q, p, kcol, spare, pf, tau_out);
     });
 }
 
@@ -324,19 +331,19 @@ __device__ __forceinline__ void triangle_to_slots(const T* tri, T (&c)[RPL][Slot
 
 // ---- the fused leaf + tree kernel --------------------------------------------
 
+// One leaf of one instance, then that instance's reduction tree: the body
+// shared by the single-matrix kernel and the batched kernel.  `a` describes the
+// instance (its matrix, leaf size and count, triangle slots, tree counters and
+// output); `leaf` is this workgroup's leaf.
 template <typename T, int NC, int RPL>
-__global__ void __launch_bounds__(kWave) tsqr_leaf_tree_kernel(LeafTreeArgs<T> a)
+__device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T>& a, int leaf, T* Rs, T* red, T* F)
 {
     constexpr int CH = 16 * RPL;                  // rows per chunk
     constexpr int NT = Tri<NC>::kSize;
     constexpr int NS = Slots<NC>::NS;
     constexpr int RPLM = (NC + 15) / 16;          // rows per lane of a merged triangle
-    __shared__ T Rs[NT];
-    __shared__ T red[kRedElems];
-    __shared__ T F[kWave];
     const int lane = threadIdx.x;
     const int q = lane >> 4, p = lane & 15;
-    const int leaf = blockIdx.x;
     const int64_t r0 = (int64_t)leaf * a.leaf_rows;
     const int64_t r1 = (r0 + a.leaf_rows < a.m) ? r0 + a.leaf_rows : a.m;
 
@@ -431,6 +438,42 @@ __global__ void __launch_bounds__(kWave) tsqr_leaf_tree_kernel(LeafTreeArgs<T> a
     }
 }
 
+template <typename T, int NC, int RPL>
+__global__ void __launch_bounds__(kWave) tsqr_leaf_tree_kernel(LeafTreeArgs<T> a)
+{
+    __shared__ T Rs[Tri<NC>::kSize + 1];          // + one spare cell
+    __shared__ T red[kRedElems];
+    __shared__ T F[kWave];
+    leaf_tree_body<T, NC, RPL>(a, blockIdx.x, Rs, red, F);
+}
+
+// Many independent instances in one launch: workgroup g takes tile
+// tiles[g] = (instance, leaf); the tiles are ordered longest first so the
+// hardware dispatcher starts the long leaves early and the short ones fill
+// in.  Every instance has its own tree, so the tree of one instance overlaps
+// the leaves of the others.
+template <typename T, int NC, int RPL>
+__global__ void __launch_bounds__(kWave) tsqr_batch_kernel(BatchArgs<T> b)
+{
+    __shared__ T Rs[Tri<NC>::kSize + 1];
+    __shared__ T red[kRedElems];
+    __shared__ T F[kWave];
+    const BatchTile t = b.tiles[blockIdx.x];
+    const BatchInstance in = b.inst[t.inst];
+    LeafTreeArgs<T> a;
+    a.A = b.A + in.a_off;
+    a.m = in.m;
+    a.lda = in.lda;
+    a.n = b.n;
+    a.leaf_rows = in.leaf_rows;
+    a.leaves = in.leaves;
+    a.tri = b.tri + in.tri_off;
+    a.tickets = b.tickets + in.ticket_off;
+    a.R = b.R + (int64_t)t.inst * b.ldr * b.n;
+    a.ldr = b.ldr;
+    leaf_tree_body<T, NC, RPL>(a, t.leaf, Rs, red, F);
+}
+
 // ---- the paper's operator as a single-workgroup kernel -------------------------
 
 template <typename T, int NC>
@@ -439,7 +482,7 @@ __global__ void __launch_bounds__(kWave) qr_uppers_kernel(int n, T* R1, T* R2, T
     constexpr int NT = Tri<NC>::kSize;
     constexpr int NS = Slots<NC>::NS;
     constexpr int RPLM = (NC + 15) / 16;
-    __shared__ T Rs[NT];
+    __shared__ T Rs[NT + 1];                      // + one spare cell
     __shared__ T red[kRedElems];
     __shared__ T F[kWave];
     __shared__ T taus[NC];

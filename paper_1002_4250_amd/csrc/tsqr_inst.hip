@@ -18,6 +18,16 @@ hipError_t TSQR_LEAF_FN2(TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL)(const LeafT
                        dim3(dev::kWave), 0, s, a);
     return hipGetLastError();
 }
+#define TSQR_BATCH_FN(tag, nc, rpl) launch_batch_##tag##_##nc##_##rpl
+#define TSQR_BATCH_FN2(tag, nc, rpl) TSQR_BATCH_FN(tag, nc, rpl)
+hipError_t TSQR_BATCH_FN2(TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL)(const BatchArgs<TSQR_INST_TAG>& a, int tiles,
+                                                                      hipStream_t s)
+{
+    if (tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL((dev::tsqr_batch_kernel<TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL>), dim3(tiles),
+                       dim3(dev::kWave), 0, s, a);
+    return hipGetLastError();
+}
 #elif defined(TSQR_INST_OP)
 #define TSQR_OP_FN(tag, nc) launch_qr_uppers_##tag##_##nc
 #define TSQR_OP_FN2(tag, nc) TSQR_OP_FN(tag, nc)

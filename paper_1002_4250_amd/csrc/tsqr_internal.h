@@ -23,16 +23,49 @@ struct LeafTreeArgs {
     int64_t ldr;
 };
 
+// Batched execution: per-instance description and the (instance, leaf) tiles.
+struct BatchInstance {
+    int64_t a_off;        // element offset of the instance's matrix in A
+    int64_t m;
+    int64_t lda;
+    int64_t leaf_rows;
+    int64_t tri_off;      // element offset of its first triangle slot in tri
+    int64_t ticket_off;   // index of its first tree counter
+    int32_t leaves;
+    int32_t pad;
+};
+
+struct BatchTile {
+    int32_t inst;
+    int32_t leaf;
+};
+
+template <typename T>
+struct BatchArgs {
+    const T* A;
+    int n;
+    const BatchInstance* inst;   // device table
+    const BatchTile* tiles;      // device table, one per workgroup
+    T* tri;
+    unsigned* tickets;
+    T* R;                        // instance b's R at R + b * ldr * n
+    int64_t ldr;
+};
+
 using f64 = double;
 using f32 = float;
 
 #define TSQR_DECLARE_LEAF(tag, NC, RPL) \
     hipError_t launch_leaf_tree_##tag##_##NC##_##RPL(const LeafTreeArgs<tag>& a, hipStream_t s);
+#define TSQR_DECLARE_BATCH(tag, NC, RPL) \
+    hipError_t launch_batch_##tag##_##NC##_##RPL(const BatchArgs<tag>& a, int tiles, hipStream_t s);
 #define TSQR_DECLARE_OP(tag, NC) \
     hipError_t launch_qr_uppers_##tag##_##NC(int n, tag* R1, tag* R2, tag* tau, hipStream_t s);
 TSQR_LEAF_INSTANCES(TSQR_DECLARE_LEAF)
+TSQR_LEAF_INSTANCES(TSQR_DECLARE_BATCH)
 TSQR_OP_INSTANCES(TSQR_DECLARE_OP)
 #undef TSQR_DECLARE_LEAF
+#undef TSQR_DECLARE_BATCH
 #undef TSQR_DECLARE_OP
 
 hipError_t launch_zero_u32(unsigned* p, int64_t count, hipStream_t s);

@@ -43,6 +43,11 @@ SIGNATURES = [
     ("tsqr_geqr_r_f32", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
     ("tsqr_qr_uppers_f64", _i, [_p, _i64, _p, _p, _p, _p]),
     ("tsqr_qr_uppers_f32", _i, [_p, _i64, _p, _p, _p, _p]),
+    ("tsqr_batch_plan_create", _i, [_p, _i64, _i64, _pi64, _pi64, _pi64, _i, ctypes.POINTER(_p)]),
+    ("tsqr_batch_plan_destroy", _i, [_p]),
+    ("tsqr_batch_workspace_bytes", _i64, [_p]),
+    ("tsqr_batch_plan_info", _i, [_p, _pi64, _pi64, _pi64]),
+    ("tsqr_batch_exec", _i, [_p, _p, _p, _i64, _p, _i64, _p]),
 ]
 
 _LOCK = threading.Lock()
@@ -216,3 +221,87 @@ def qr_uppers(R1, R2, tau=None, h=None):
     st = fn(h, n, R1.data_ptr(), R2.data_ptr(), tau.data_ptr(), _stream_ptr(torch, R1.device))
     _check(fn.__name__, st, h)
     return R1, R2, tau[:n]
+
+
+# ---- batched ---------------------------------------------------------------
+
+def _i64_array(values):
+    import numpy as np
+    a = np.ascontiguousarray(values, dtype=np.int64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def tsqr_batch_plan_create(handle, batch, n, m, a_offset, lda, dtype) -> int:
+    """Plan for `batch` matrices; m, a_offset, lda are host integer sequences
+    (lda may be None).  Returns the plan handle."""
+    m_arr, m_p = _i64_array(m)
+    o_arr, o_p = _i64_array(a_offset)
+    if lda is None:
+        l_p = ctypes.cast(None, ctypes.POINTER(ctypes.c_int64))
+    else:
+        l_arr, l_p = _i64_array(lda)
+    plan = ctypes.c_void_p()
+    st = lib().tsqr_batch_plan_create(handle, int(batch), int(n), m_p, o_p, l_p, int(dtype), ctypes.byref(plan))
+    _check("tsqr_batch_plan_create", st, handle)
+    return plan.value
+
+
+def tsqr_batch_plan_destroy(plan) -> None:
+    lib().tsqr_batch_plan_destroy(plan)
+
+
+def tsqr_batch_workspace_bytes(plan) -> int:
+    v = lib().tsqr_batch_workspace_bytes(plan)
+    if v < 0:
+        raise TsqrError("tsqr_batch_workspace_bytes", int(v))
+    return int(v)
+
+
+def tsqr_batch_plan_info(plan):
+    t, l, r = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check("tsqr_batch_plan_info", lib().tsqr_batch_plan_info(plan, ctypes.byref(t), ctypes.byref(l), ctypes.byref(r)))
+    return t.value, l.value, r.value
+
+
+def tsqr_batch_exec(plan, A, R, ldr, ws, ws_bytes, stream) -> int:
+    return lib().tsqr_batch_exec(plan, A, R, ldr, ws, ws_bytes, stream)
+
+
+class BatchPlan:
+    """Plan + workspace for a ragged batch held in one flat device tensor
+    (instance b is the m[b]-by-n column-major block at element offset
+    offsets[b]).  ``run(A_flat)`` returns a (batch, n, n) tensor whose [b] is
+    instance b's R stored column-major (R[b].t() is the usual n x n view)."""
+
+    def __init__(self, sizes, offsets, n, dtype, device=None, h=None):
+        import torch
+        self.torch = torch
+        self.dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.h = h or handle(self.dev.index or 0)
+        self.n = int(n)
+        self.batch = len(sizes)
+        self.dtype = dtype
+        code = TSQR_F64 if dtype == torch.float64 else TSQR_F32
+        self.plan = tsqr_batch_plan_create(self.h, self.batch, self.n, sizes, offsets, None, code)
+        nbytes = max(tsqr_batch_workspace_bytes(self.plan), 256)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.dev)
+
+    def info(self):
+        return tsqr_batch_plan_info(self.plan)
+
+    def run(self, A_flat, R=None):
+        torch = self.torch
+        if R is None:
+            R = torch.empty((self.batch, self.n, self.n), dtype=self.dtype, device=self.dev)
+        st = tsqr_batch_exec(self.plan, A_flat.data_ptr(), R.data_ptr(), self.n, self.ws.data_ptr(),
+                             self.ws.numel(), _stream_ptr(torch, self.dev))
+        _check("tsqr_batch_exec", st, self.h)
+        return R
+
+    def __del__(self):
+        try:
+            if getattr(self, "plan", None):
+                tsqr_batch_plan_destroy(self.plan)
+                self.plan = None
+        except Exception:
+            pass

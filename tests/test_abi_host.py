@@ -128,3 +128,92 @@ def test_create_without_gpu_reports_no_device():
     h = ctypes.c_void_p()
     assert tsqr.lib().tsqr_create(ctypes.byref(h), 0) == tsqr.TSQR_ERR_NO_DEVICE
     assert not h.value
+
+
+def _batch_create(h, sizes, n, dtype=tsqr.TSQR_F64, offsets=None, lda=None):
+    import numpy as np
+    sizes = np.asarray(sizes, dtype=np.int64)
+    if offsets is None:
+        offsets = np.concatenate([[0], np.cumsum(sizes * n)[:-1]]).astype(np.int64) if len(sizes) else sizes
+    return tsqr.tsqr_batch_plan_create(h, len(sizes), n, sizes, offsets, lda, dtype)
+
+
+def test_batch_plan_tiles_and_workspace(ph):
+    # ragged sizes: each instance is cut into ceil(m/L) leaves of L rows
+    # (m = 0 still has one empty leaf that writes a zero R)
+    sizes = [64, 1000, 0, 1, 65536, 4097]
+    p = _batch_create(ph, sizes, 50)
+    try:
+        tiles, leaves, L = tsqr.tsqr_batch_plan_info(p)
+        assert L == 32 * 16 * 8
+        want = sum(max(1, -(-m // L)) for m in sizes)
+        assert tiles == leaves == want
+        tri = 50 * 51 // 2
+        align = lambda x: (x + 255) // 256 * 256
+        assert tsqr.tsqr_batch_workspace_bytes(p) == align(4 * leaves) + align(8 * tri * leaves)
+    finally:
+        tsqr.tsqr_batch_plan_destroy(p)
+    # fp32 and a handle leaf size
+    tsqr.tsqr_set_option(ph, tsqr.TSQR_OPT_LEAF_ROWS, 1000)
+    p = _batch_create(ph, sizes, 16, tsqr.TSQR_F32)
+    try:
+        tiles, leaves, L = tsqr.tsqr_batch_plan_info(p)
+        assert L == 1024
+        assert tiles == sum(max(1, -(-m // 1024)) for m in sizes)
+        assert tsqr.tsqr_batch_workspace_bytes(p) == (4 * tiles + 255) // 256 * 256 + \
+            (4 * 136 * tiles + 255) // 256 * 256
+    finally:
+        tsqr.tsqr_batch_plan_destroy(p)
+
+
+def test_batch_plan_argument_checks(ph):
+    import numpy as np
+    L = tsqr.lib()
+    P = ctypes.POINTER(ctypes.c_int64)
+    m = (ctypes.c_int64 * 2)(10, 20)
+    off = (ctypes.c_int64 * 2)(0, 100)
+    out = ctypes.c_void_p()
+    assert L.tsqr_batch_plan_create(None, 2, 4, m, off, None, 0, ctypes.byref(out)) == -1
+    assert L.tsqr_batch_plan_create(ph, -1, 4, m, off, None, 0, ctypes.byref(out)) == -2
+    assert L.tsqr_batch_plan_create(ph, 2, -1, m, off, None, 0, ctypes.byref(out)) == -3
+    assert L.tsqr_batch_plan_create(ph, 2, 4, None, off, None, 0, ctypes.byref(out)) == -4
+    bad_m = (ctypes.c_int64 * 2)(10, -1)
+    assert L.tsqr_batch_plan_create(ph, 2, 4, bad_m, off, None, 0, ctypes.byref(out)) == -4
+    assert L.tsqr_batch_plan_create(ph, 2, 4, m, None, None, 0, ctypes.byref(out)) == -5
+    bad_off = (ctypes.c_int64 * 2)(0, -5)
+    assert L.tsqr_batch_plan_create(ph, 2, 4, m, bad_off, None, 0, ctypes.byref(out)) == -5
+    bad_lda = (ctypes.c_int64 * 2)(10, 19)
+    assert L.tsqr_batch_plan_create(ph, 2, 4, m, off, bad_lda, 0, ctypes.byref(out)) == -6
+    assert L.tsqr_batch_plan_create(ph, 2, 4, m, off, None, 7, ctypes.byref(out)) == -7
+    assert L.tsqr_batch_plan_create(ph, 2, 4, m, off, None, 0, None) == -8
+    assert L.tsqr_batch_plan_create(ph, 2, 65, m, off, None, 0, ctypes.byref(out)) == tsqr.TSQR_ERR_UNSUPPORTED
+    # exec checks on a planning handle's plan
+    assert L.tsqr_batch_plan_create(ph, 2, 4, m, off, None, 0, ctypes.byref(out)) == 0
+    p = out.value
+    try:
+        need = L.tsqr_batch_workspace_bytes(p)
+        buf = ctypes.create_string_buffer(need + 512)
+        ws = (ctypes.addressof(buf) + 255) // 256 * 256
+        assert L.tsqr_batch_exec(None, 1, 1, 4, ws, need, None) == -1
+        assert L.tsqr_batch_exec(p, None, 1, 4, ws, need, None) == -2
+        assert L.tsqr_batch_exec(p, 1, None, 4, ws, need, None) == -3
+        assert L.tsqr_batch_exec(p, 1, 1, 3, ws, need, None) == -4
+        assert L.tsqr_batch_exec(p, 1, 1, 4, None, need, None) == -5
+        assert L.tsqr_batch_exec(p, 1, 1, 4, ws + 8, need, None) == -5
+        assert L.tsqr_batch_exec(p, 1, 1, 4, ws, need - 1, None) == -6
+        assert L.tsqr_batch_exec(p, 1, 1, 4, ws, need, None) == tsqr.TSQR_ERR_NO_DEVICE
+    finally:
+        L.tsqr_batch_plan_destroy(p)
+    assert L.tsqr_batch_workspace_bytes(None) == -1
+    assert L.tsqr_batch_plan_destroy(None) == 0
+
+
+def test_batch_plan_empty(ph):
+    import numpy as np
+    p = tsqr.tsqr_batch_plan_create(ph, 0, 50, np.zeros(0, np.int64), np.zeros(0, np.int64), None, 0)
+    try:
+        assert tsqr.tsqr_batch_plan_info(p) == (0, 0, 32 * 16 * 8)
+        # nothing to do: succeeds without touching any pointer
+        assert tsqr.lib().tsqr_batch_exec(p, None, None, 50, None, 0, None) == 0
+    finally:
+        tsqr.tsqr_batch_plan_destroy(p)
