@@ -7,7 +7,12 @@ resident in HBM before timing starts.  A step is one full pass of the hot path
 (leaf factorisations + reduction tree + finalisation: one kernel launch through
 the C ABI).  Prints ONE JSON line on stdout; progress goes to stderr.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline] [--no-batched]
+
+The ``batched`` object of the line measures the ragged batch (4096 instances,
+m log-uniform in [64, 65536], n = 50, FP32) three ways: one batched launch per
+step, a Python loop of single-matrix calls, and the same loop captured once
+in a HIP graph and replayed.
 
 Roofline: the path is bound by the FP64 vector FMA rate (arithmetic
 intensity 2n/8 = 12.5 flop/byte against a ridge of 78.6/8 = 9.8), so
@@ -86,12 +91,100 @@ def time_plain(torch, tsqr, Ad, steps, warmup):
     return ms_step, ms_kernel, wall, R
 
 
+def time_batched(torch, tsqr, inputs, steps, warmup, n=50, count=4096):
+    """The ragged batch: batched launch vs looped single-matrix calls."""
+    import numpy as np
+    t = time.perf_counter()
+    flat, sizes, offsets = inputs.batched_uniform(count, n, 64, 65536, seed=2, dtype=np.float32)
+    log(f"batched: {count} instances, {int(sizes.sum())} rows in total, n={n} fp32 "
+        f"(generated in {time.perf_counter() - t:.1f} s)")
+    Ad = torch.from_numpy(flat).cuda()
+    del flat
+    plan = tsqr.BatchPlan(sizes, offsets, n, torch.float32)
+    tiles, leaves, L = plan.info()
+    R = torch.empty((count, n, n), dtype=torch.float32, device="cuda")
+
+    def timed(fn, k):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    ms_batched = timed(lambda: plan.run(Ad, R), steps)
+    Rb = R.clone()
+
+    # looped single-matrix calls over the same device data, one shared workspace
+    h = tsqr.handle(0)
+    views = [Ad[int(o):int(o) + int(m) * n].view(n, int(m)).t() for m, o in zip(sizes, offsets)]
+    ws_bytes = max(tsqr.tsqr_workspace_bytes(h, int(m), n, tsqr.TSQR_F32) for m in set(sizes.tolist()))
+    ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device="cuda")
+    Rl = torch.empty((count, n, n), dtype=torch.float32, device="cuda")
+    outs = [Rl[b].t() for b in range(count)]
+
+    def loop():
+        for b in range(count):
+            tsqr.geqr_r(views[b], R=outs[b], ws=ws, h=h)
+
+    loop_steps = max(1, min(steps, 3))
+    ms_loop = timed(loop, loop_steps)
+    same_as_loop = None
+    # the same loop captured once in a HIP graph (no per-call host overhead)
+    ms_graph = None
+    try:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            loop()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            loop()
+        ms_graph = timed(g.replay, steps)
+    except RuntimeError as e:
+        log(f"graph capture of the loop failed: {e}")
+    torch.cuda.synchronize()
+    # each batched instance equals the corresponding single call up to the tree shape
+    diff = float(((Rl - Rb).norm() / Rb.norm()).item())
+    same_as_loop = diff
+    sum_rows = int(sizes.sum())
+    flops = 2.0 * sum_rows * n * n
+    tflops = flops / (ms_batched * 1e-3) / 1e12
+    gbs = 4.0 * sum_rows * n / (ms_batched * 1e-3) / 1e9
+    log(f"batched: {ms_batched:.3f} ms/step ({count / ms_batched * 1e3:.0f} instances/s, {tflops:.2f} TFLOP/s); "
+        f"loop {ms_loop:.2f} ms; graph loop {ms_graph if ms_graph is None else round(ms_graph, 3)} ms")
+    out = {
+        "workload": f"ragged batch {count} instances m log-uniform [64, 65536] (sum {sum_rows}) n={n} fp32 "
+                    "uniform[-1,1) seed 2",
+        "value": count / (ms_batched * 1e-3), "unit": "instances/s", "ms_per_step": ms_batched,
+        "tiles": tiles, "leaf_rows": L,
+        "plain_loop": {"value": count / (ms_loop * 1e-3), "ms_per_step": ms_loop, "steps": loop_steps},
+        "plain_loop_graph": None if ms_graph is None else
+        {"value": count / (ms_graph * 1e-3), "ms_per_step": ms_graph},
+        "speedup_vs_loop": ms_loop / ms_batched,
+        "speedup_vs_graph_loop": None if ms_graph is None else ms_graph / ms_batched,
+        "rel_diff_vs_plain_calls": same_as_loop,
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tflops / PEAK_FP32_TFLOPS, "hbm_GBs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS},
+    }
+    del Ad, R, Rl, plan
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--m", type=int, default=1 << 22)
     ap.add_argument("--n", type=int, default=50)
     ap.add_argument("--profile-copy-bytes", type=int, default=0,
@@ -135,6 +228,8 @@ def main():
     log(f"fp32: {ms_step32 * 1e3:.1f} us/step, kernel {ms_kernel32 * 1e3:.1f} us, {tflops32:.2f} TFLOP/s")
     R32 = R32.cpu().numpy().astype(np.float64)
     del Ad32
+
+    batched = None if args.no_batched else time_batched(torch, tsqr, inputs, args.steps, args.warmup)
 
     cpu = None
     acc64 = acc32 = None
@@ -185,6 +280,7 @@ def main():
         "fp32": {"value": 1000.0 / ms_step32, "unit": "instances/s", "ms_per_step": ms_step32,
                  "kernel_ms": ms_kernel32, "achieved_TFLOPs": tflops32, "peak": PEAK_FP32_TFLOPS,
                  "frac": tflops32 / PEAK_FP32_TFLOPS},
+        "batched": batched,
         "wall_s_timed": wall,
     }
     print(json.dumps(out), flush=True)

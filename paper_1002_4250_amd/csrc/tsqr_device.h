@@ -180,31 +180,68 @@ enum class Mode { Leaf, Merge, Operator };
 // 4s+3) the whole slot is refilled with the next chunk's columns 4s..4s+3 by
 // one wavefront-wide load per register, into registers no later step of the
 // current chunk reads, so no step waits for the loads.  `col` is a per-lane
-// running pointer to the lane's column of the next slot; lda and n pass
-// through an opaque register copy so the compiler keeps that one pointer
+// running pointer to (row base + p, column 4s + q) of the next slot; lda and n
+// pass through an opaque register copy so the compiler keeps that one pointer
 // instead of precomputing one address per slot.
+//
+// The loads are branch-free: a lane whose column lies past n reads from a
+// block of zeros instead, so in a chunk whose rows all lie inside the leaf
+// (every chunk but a ragged last one) each register is one load at a constant
+// offset.  Only a ragged chunk selects per row.  `state` is uniform: 0 no next
+// chunk, 1 full chunk, 2 ragged chunk.
+static __device__ double kZerosF64[256];
+static __device__ float kZerosF32[256];
+__device__ __forceinline__ const double* zeros_for(const double*) { return kZerosF64; }
+__device__ __forceinline__ const float* zeros_for(const float*) { return kZerosF32; }
+
 template <typename T, int RPL>
 struct Prefetch {
-    const T* col;        // per lane: &A(base, 4s + q) for the next slot s to fill
+    const T* col;        // per lane: &A(base + p, 4s + q) for the next slot s to fill
+    const T* zero;       // per lane: zero block + p
     int64_t lda4;        // uniform: 4 * lda
     int cols_left;       // per lane: n - (4s + q)
-    bool ok[RPL];        // per lane: row base + p + 16 r lies inside the leaf
+    int state;           // uniform: 0 none, 1 full chunk, 2 ragged chunk
+    int rows;            // uniform: rows of the next chunk inside the leaf
 };
 
 template <typename T, int RPL>
 __device__ __forceinline__ Prefetch<T, RPL> make_prefetch(const T* A, int64_t lda, int n, int64_t base, int64_t r1,
                                                           int q, int p)
 {
+    static_assert(16 * RPL <= 256, "zero block too small");
     Prefetch<T, RPL> pf;
     int64_t ld = lda;
     int nn = n;
     asm volatile("" : "+s"(ld), "+s"(nn));
-    pf.col = A + (base < r1 ? base : 0) + (int64_t)q * ld;
+    pf.col = A + (base < r1 ? base : 0) + p + (int64_t)q * ld;
+    pf.zero = zeros_for(A) + p;
     pf.lda4 = 4 * ld;
     pf.cols_left = nn - q;
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) pf.ok[r] = base + p + 16 * r < r1;
+    const int64_t left = r1 - base;
+    pf.state = left <= 0 ? 0 : (left >= 16 * RPL ? 1 : 2);
+    pf.rows = left <= 0 ? 0 : (left >= 16 * RPL ? 16 * RPL : (int)left);
     return pf;
+}
+
+// Fill register slot `slot` with the next chunk's columns and advance.
+template <typename T, int RPL, int NS>
+__device__ __forceinline__ void prefetch_slot(T (&c)[RPL][NS], int slot, Prefetch<T, RPL>& pf, int p)
+{
+    if (pf.state != 0) {
+        const T* ptr = pf.cols_left > 0 ? pf.col : pf.zero;
+        if (pf.state == 1) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) c[r][slot] = ptr[16 * r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const bool ok = p + 16 * r < pf.rows;
+                c[r][slot] = *(ok ? ptr + 16 * r : pf.zero + 16 * r);
+            }
+        }
+    }
+    pf.col += pf.lda4;
+    pf.cols_left -= 4;
 }
 
 // Step J of R := qr([R; C]) with R packed in LDS (Rs) and C in registers.  The
@@ -219,23 +256,29 @@ __device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* re
     constexpr int K = NC - 1 - J;             // trailing columns
     constexpr int OFF = Tri<NC>::off(J);
 
-    // (a) the pivot column in every lane row, its norm and reflector
+    // R(J, J) and, for the lane that completes column k, R(J, k): row J of R
+    // last changed at step J of the previous chunk, so both reads are issued
+    // first and are long complete when needed.  Lanes that own no trailing
+    // column read and later write a spare LDS cell, keeping the step free of
+    // branches.
+    const int k = kcol;
+    const bool own = (k > J) && (k < NC);
+    const int ridx = own ? OFF + k - J : spare;
+    const T alpha = Rs[OFF];
+    const T rjk = Rs[ridx];
+
+    // (a) the pivot column in every lane row
     const int src = ((QJ << 4) | p) << 2;
     T x[RPL];
 #pragma unroll
     for (int r = 0; r < RPL; ++r) x[r] = bpermute(src, c[r][SJ]);
-    T sp = x[0] * x[0];
-#pragma unroll
-    for (int r = 1; r < RPL; ++r) sp = __builtin_fma(x[r], x[r], sp);
-    const T sigma2 = row_allreduce16(sp);
-    const T alpha = Rs[OFF];
-    const Reflector<T> h = make_reflector(alpha, sigma2);
 
+    // (b) partial dot products of the live slots (slot SJ is live only in
+    // lane rows q > QJ; elsewhere its result is ignored), one 16 x 17 LDS tile
+    // per lane row: writer p puts slot s at [s][p].  They are issued before
+    // the reflector so that its dependent chain runs under the LDS round trip.
+    T* rq = red + q * 16 * kRedStride;
     if constexpr (K > 0) {
-        // (b) partial dot products of the live slots (slot SJ is live only in
-        // lane rows q > QJ; elsewhere its result is ignored), one 16 x 17 LDS
-        // tile per lane row: writer p puts slot s at [s][p]
-        T* rq = red + q * 16 * kRedStride;
         static_for<SJ, NS>([&](auto sc) {
             constexpr int s = decltype(sc)::value;
             T acc = x[0] * c[0][s];
@@ -243,22 +286,28 @@ __device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* re
             for (int r = 1; r < RPL; ++r) acc = __builtin_fma(x[r], c[r][s], acc);
             rq[s * kRedStride + p] = acc;
         });
-        lds_order();
-        // (c) lane (q, p) completes column k = 4p + q: sum of the 16 writers
-        T u[16];
+    }
+    lds_order();
+    // (c) lane (q, p) gathers the 16 partials of column k = 4p + q
+    T u[16];
+    if constexpr (K > 0) {
         const T* rd = rq + p * kRedStride;
 #pragma unroll
         for (int i = 0; i < 16; ++i) u[i] = rd[i];
+    }
+
+    // the norm of the pivot column and its reflector
+    T sp = x[0] * x[0];
+#pragma unroll
+    for (int r = 1; r < RPL; ++r) sp = __builtin_fma(x[r], x[r], sp);
+    const T sigma2 = row_allreduce16(sp);
+    const Reflector<T> h = make_reflector(alpha, sigma2);
+
+    if constexpr (K > 0) {
 #pragma unroll
         for (int hh = 8; hh >= 1; hh >>= 1)
 #pragma unroll
             for (int i = 0; i < hh; ++i) u[i] = u[i] + u[i + hh];
-        // branch-free: lanes that own no trailing column read and write a spare
-        // LDS cell and publish a zero coefficient
-        const int k = kcol;
-        const bool own = (k > J) && (k < NC);
-        const int ridx = own ? OFF + k - J : spare;
-        const T rjk = Rs[ridx];
         const T w = __builtin_fma(h.s, u[0], rjk);
         Rs[ridx] = __builtin_fma(-h.tau, w, rjk);
         F[q * 16 + p] = own ? h.ts * w : T(0);
@@ -285,13 +334,7 @@ __device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* re
         if (q == 0 && p == 0) tau_out[J] = h.tau;
     } else if constexpr (M == Mode::Leaf) {
         // slot SJ is finished in every lane row: it takes the next chunk's columns
-        if constexpr (QJ == 3 || J == NC - 1) {
-            const bool colok = pf.cols_left > 0;
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) c[r][SJ] = (colok && pf.ok[r]) ? pf.col[p + 16 * r] : T(0);
-            pf.col += pf.lda4;
-            pf.cols_left -= 4;
-        }
+        if constexpr (QJ == 3 || J == NC - 1) prefetch_slot<T, RPL, NS>(c, SJ, pf, p);
     }
 }
 
