@@ -54,8 +54,18 @@ constexpr int kRedElems = 4 * 16 * kRedStride;  // one 16 x 17 tile per lane row
 template <int NC>
 struct Tri {
     static constexpr int kSize = NC * (NC + 1) / 2;
+    // LDS copies get one wavefront of padding: a spare cell for branch-free
+    // writes and room for column reads of lanes past the triangle
+    static constexpr int kPadded = kSize + 64;
     // packed row-major upper triangle: row j starts at off(j), entry (j,k) at off(j)+k-j
     static constexpr __host__ __device__ int off(int j) { return j * NC - (j * (j - 1)) / 2; }
+};
+
+// The leaf's reduction tiles and, in the tree, the partner's triangle share
+// one LDS buffer: they are never live at the same time.
+template <int NC>
+struct LdsScratch {
+    static constexpr int kElems = kRedElems > Tri<NC>::kPadded ? kRedElems : Tri<NC>::kPadded;
 };
 
 template <int NC>
@@ -115,6 +125,18 @@ __device__ __forceinline__ float bpermute(int src, float x)
     return __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(x)));
 }
 
+// Value of x in lane `l` (l uniform), for every lane.
+__device__ __forceinline__ double lane_value(double x, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_value(float x, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }
 
 // Orders this wavefront's LDS accesses around a point without constraining
@@ -171,9 +193,7 @@ __device__ __forceinline__ Reflector<T> make_reflector(T alpha, T sigma2)
     return r;
 }
 
-// ---- one Householder step ----------------------------------------------------
-
-enum class Mode { Leaf, Merge, Operator };
+// ---- one Householder step of a leaf -------------------------------------------
 
 // Where a leaf prefetches its next chunk from.  A register slot holds four
 // columns (one per lane row); once its four columns are finished (after step
@@ -247,9 +267,9 @@ __device__ __forceinline__ void prefetch_slot(T (&c)[RPL][NS], int slot, Prefetc
 // Step J of R := qr([R; C]) with R packed in LDS (Rs) and C in registers.  The
 // NC steps of a chunk are unrolled at compile time so every register index is
 // static and the scheduler can overlap consecutive steps.
-template <typename T, int NC, int RPL, Mode M, int J>
+template <typename T, int NC, int RPL, int J>
 __device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* red, T* F, int q, int p,
-                                        int kcol, int spare, Prefetch<T, RPL>& pf, T* tau_out)
+                                        int kcol, int spare, Prefetch<T, RPL>& pf)
 {
     constexpr int NS = Slots<NC>::NS;
     constexpr int QJ = J % 4, SJ = J / 4;     // lane row and slot holding column J
@@ -325,22 +345,14 @@ __device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* re
         });
     }
 
-    // (e) the pivot column's registers (lane row QJ, slot SJ)
-    if constexpr (M == Mode::Operator) {
-        // the Householder vector v = s x replaces x (identity reflector: x kept)
-        const bool mine = (q == QJ) && (h.tau != T(0));
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) c[r][SJ] = mine ? h.s * x[r] : c[r][SJ];
-        if (q == 0 && p == 0) tau_out[J] = h.tau;
-    } else if constexpr (M == Mode::Leaf) {
-        // slot SJ is finished in every lane row: it takes the next chunk's columns
-        if constexpr (QJ == 3 || J == NC - 1) prefetch_slot<T, RPL, NS>(c, SJ, pf, p);
-    }
+    // (e) slot SJ is finished in every lane row once its last column is the
+    // pivot: it takes the next chunk's columns
+    if constexpr (QJ == 3 || J == NC - 1) prefetch_slot<T, RPL, NS>(c, SJ, pf, p);
 }
 
-template <typename T, int NC, int RPL, Mode M>
+template <typename T, int NC, int RPL>
 __device__ __forceinline__ void merge_chunk(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* red, T* F, int q, int p,
-                                            Prefetch<T, RPL>& pf, T* tau_out)
+                                            Prefetch<T, RPL>& pf)
 {
     // the column a lane completes in the reduction, passed through an opaque
     // copy so the compiler does not precompute (and keep live) one
@@ -349,26 +361,104 @@ __device__ __forceinline__ void merge_chunk(T (&c)[RPL][Slots<NC>::NS], T* Rs, T
     asm volatile("" : "+v"(kcol));
     const int spare = Tri<NC>::kSize;      // one LDS cell past the triangle
     static_for<0, NC>([&](auto jc) {
-        hh_step<T, NC, RPL, M, decltype(jc)::value>(c, Rs, red, F, q, p, kcol, spare, pf, tau_out);
+        hh_step<T, NC, RPL, decltype(jc)::value>(c, Rs, red, F, q, p, kcol, spare, pf);
     });
 }
 
-// Load the packed triangle `tri` (NC*(NC+1)/2 values, rows packed; LDS or
-// global) into the chunk layout: row i = p + 16r, column k = 4s + q holds
-// R(i, k) for i <= k < NC, zero elsewhere.
-template <typename T, int NC, int RPL>
-__device__ __forceinline__ void triangle_to_slots(const T* tri, T (&c)[RPL][Slots<NC>::NS], int q, int p)
+// ---- the operator with one column per lane -------------------------------------
+//
+// R := qr([R1; R2]) for two NC x NC upper triangles, the operator of section 2
+// in the structured form of Table 3 (only rows 0..J of R2 take part in step J).
+// R1 is packed by rows in LDS (Rs, with one spare cell after it); lane k holds
+// column k of R2 in registers (v[i] = R2(i, k), zero below the diagonal).  In
+// step J the pivot lane J publishes R2(0:J, J) through LDS; every lane then
+// forms its own dot product with it locally (lane J's is sigma^2, read by all
+// lanes from its register), so a step has a single LDS round trip and no
+// cross-lane reduction, and lane k > J updates R1(J, k) and its column.  Used by the reduction tree and the operator entry point,
+// where the operands have only NC rows and the length of the dependent chain
+// of NC steps, not the arithmetic, sets the time.
+//
+// Mode::Operator also leaves the Householder vectors in v (lane J's column
+// becomes s x, or stays x for an identity reflector) and the tau in tau_out.
+enum class Mode { Merge, Operator };
+
+template <typename T, int NC, Mode M>
+__device__ __forceinline__ void merge_columns(T (&v)[NC], T* Rs, T* xb, T* tau_out)
 {
-    constexpr int NS = Slots<NC>::NS;
+    const int lane = threadIdx.x;
+    static_for<0, NC>([&](auto jc) {
+        constexpr int J = decltype(jc)::value;
+        constexpr int OFF = Tri<NC>::off(J);
+        const bool own = (lane > J) && (lane < NC);
+        const int ridx = own ? OFF + lane - J : Tri<NC>::kSize;
+        const T alpha = Rs[OFF];
+        const T rjk = Rs[ridx];
+        if (lane == J) {
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-        const int i = p + 16 * r;
-        const int base = (i < NC) ? Tri<NC>::off(i) - i : 0;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int k = 4 * s + q;
-            c[r][s] = (i < NC && k < NC && k >= i) ? tri[base + k] : T(0);
+            for (int i = 0; i <= J; ++i) xb[i] = v[i];
         }
+        lds_order();
+        T x[J + 1];
+#pragma unroll
+        for (int i = 0; i <= J; ++i) x[i] = xb[i];
+        // this lane's dot product with the pivot column (two accumulators);
+        // for lane J it is sigma^2 itself
+        T d0 = x[0] * v[0], d1 = T(0);
+#pragma unroll
+        for (int i = 1; i <= J; ++i) {
+            if (i & 1) d1 = __builtin_fma(x[i], v[i], d1);
+            else d0 = __builtin_fma(x[i], v[i], d0);
+        }
+        const T d = d0 + d1;
+        const Reflector<T> h = make_reflector(alpha, lane_value(d, J));
+        const T w = __builtin_fma(h.s, d, rjk);
+        Rs[ridx] = __builtin_fma(-h.tau, w, rjk);
+        const T f = own ? h.ts * w : T(0);
+#pragma unroll
+        for (int i = 0; i <= J; ++i) v[i] = __builtin_fma(-f, x[i], v[i]);
+        if constexpr (M == Mode::Operator) {
+            const bool mine = (lane == J) && (h.tau != T(0));
+#pragma unroll
+            for (int i = 0; i <= J; ++i) v[i] = mine ? h.s * x[i] : v[i];
+            if (lane == 0) tau_out[J] = h.tau;
+        }
+        if (lane == 0) Rs[OFF] = h.beta;
+        lds_order();
+    });
+}
+
+// Column `lane` of a packed NC x NC upper triangle held in LDS (rows packed,
+// buffer padded to Tri<NC>::kPadded elements so every lane's reads stay inside
+// it) into registers, zero below the diagonal and past column NC.
+template <typename T, int NC>
+__device__ __forceinline__ void triangle_column(const T* tri, T (&v)[NC])
+{
+    const int k = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        const T t = tri[k + (Tri<NC>::off(i) - i)];
+        v[i] = (i <= k && k < NC) ? t : T(0);
+    }
+}
+
+// Copy a packed triangle from global memory to LDS: all loads first, then
+// all stores, so the loads are in flight together.
+template <typename T, int NC>
+__device__ __forceinline__ void triangle_to_lds(const T* __restrict__ src, T* dst)
+{
+    constexpr int NT = Tri<NC>::kSize;
+    constexpr int U = (NT + kWave - 1) / kWave;
+    const int lane = threadIdx.x;
+    T t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int i = lane + u * kWave;
+        t[u] = src[i < NT ? i : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int i = lane + u * kWave;
+        if (i < NT) dst[i] = t[u];
     }
 }
 
@@ -384,7 +474,6 @@ __device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T>& a, int lea
     constexpr int CH = 16 * RPL;                  // rows per chunk
     constexpr int NT = Tri<NC>::kSize;
     constexpr int NS = Slots<NC>::NS;
-    constexpr int RPLM = (NC + 15) / 16;          // rows per lane of a merged triangle
     const int lane = threadIdx.x;
     const int q = lane >> 4, p = lane & 15;
     const int64_t r0 = (int64_t)leaf * a.leaf_rows;
@@ -411,7 +500,7 @@ __device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T>& a, int lea
         const int64_t nchunks = (r1 - r0 + CH - 1) / CH;
         for (int64_t t = 0; t < nchunks; ++t) {
             Prefetch<T, RPL> pf = make_prefetch<T, RPL>(a.A, a.lda, a.n, r0 + (t + 1) * CH, r1, q, p);
-            merge_chunk<T, NC, RPL, Mode::Leaf>(c, Rs, red, F, q, p, pf, nullptr);
+            merge_chunk<T, NC, RPL>(c, Rs, red, F, q, p, pf);
         }
     }
     wave_sync();
@@ -444,20 +533,20 @@ __device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T>& a, int lea
         __threadfence();
         if (lane == 0) a.tickets[id] = 0u;      // both arrived: reset for the next call
 
-        T c1[RPLM][NS];
+        T v[NC];
         if (is_left) {
-            triangle_to_slots<T, NC, RPLM>(a.tri + (int64_t)partner * NT, c1, q, p);
+            triangle_to_lds<T, NC>(a.tri + (int64_t)partner * NT, red);
+            wave_sync();
+            triangle_column<T, NC>(red, v);
         } else {
             // this wavefront holds the right (lower) operand: move it to registers
             // and bring the left one into LDS, keeping the lower index on top
-            triangle_to_slots<T, NC, RPLM>(Rs, c1, q, p);
+            triangle_column<T, NC>(Rs, v);
             wave_sync();
-            const T* lt = a.tri + (int64_t)partner * NT;
-            for (int i = lane; i < NT; i += kWave) Rs[i] = lt[i];
+            triangle_to_lds<T, NC>(a.tri + (int64_t)partner * NT, Rs);
         }
         wave_sync();
-        Prefetch<T, RPLM> none{};
-        merge_chunk<T, NC, RPLM, Mode::Merge>(c1, Rs, red, F, q, p, none, nullptr);
+        merge_columns<T, NC, Mode::Merge>(v, Rs, red, nullptr);
         wave_sync();
         node = left;
         ++level;
@@ -481,13 +570,26 @@ __device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T>& a, int lea
     }
 }
 
+// Workgroups are dispatched to the 8 XCDs in turn (workgroup g to XCD g mod 8),
+// and each XCD has its own L2.  With P = 8a + b leaves, XCD x runs a + [x < b]
+// workgroups; giving them the consecutive leaves starting at x a + min(x, b)
+// makes tree siblings share an XCD at every level below the top three, so the
+// stores, counters and loads of those merges stay in one L2.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_local_leaf(int g, int P)
+{
+    const int a = P / kXcds, b = P % kXcds, x = g % kXcds;
+    return x * a + (x < b ? x : b) + g / kXcds;
+}
+
 template <typename T, int NC, int RPL>
 __global__ void __launch_bounds__(kWave) tsqr_leaf_tree_kernel(LeafTreeArgs<T> a)
 {
-    __shared__ T Rs[Tri<NC>::kSize + 1];          // + one spare cell
-    __shared__ T red[kRedElems];
+    __shared__ T Rs[Tri<NC>::kPadded];
+    __shared__ T red[LdsScratch<NC>::kElems];
     __shared__ T F[kWave];
-    leaf_tree_body<T, NC, RPL>(a, blockIdx.x, Rs, red, F);
+    leaf_tree_body<T, NC, RPL>(a, xcd_local_leaf(blockIdx.x, a.leaves), Rs, red, F);
 }
 
 // Many independent instances in one launch: workgroup g takes tile
@@ -498,8 +600,8 @@ __global__ void __launch_bounds__(kWave) tsqr_leaf_tree_kernel(LeafTreeArgs<T> a
 template <typename T, int NC, int RPL>
 __global__ void __launch_bounds__(kWave) tsqr_batch_kernel(BatchArgs<T> b)
 {
-    __shared__ T Rs[Tri<NC>::kSize + 1];
-    __shared__ T red[kRedElems];
+    __shared__ T Rs[Tri<NC>::kPadded];
+    __shared__ T red[LdsScratch<NC>::kElems];
     __shared__ T F[kWave];
     const BatchTile t = b.tiles[blockIdx.x];
     const BatchInstance in = b.inst[t.inst];
@@ -523,48 +625,32 @@ template <typename T, int NC>
 __global__ void __launch_bounds__(kWave) qr_uppers_kernel(int n, T* R1, T* R2, T* tau)
 {
     constexpr int NT = Tri<NC>::kSize;
-    constexpr int NS = Slots<NC>::NS;
-    constexpr int RPLM = (NC + 15) / 16;
-    __shared__ T Rs[NT + 1];                      // + one spare cell
-    __shared__ T red[kRedElems];
-    __shared__ T F[kWave];
+    __shared__ T Rs[Tri<NC>::kPadded];
+    __shared__ T R2s[Tri<NC>::kPadded];
     __shared__ T taus[NC];
     const int lane = threadIdx.x;
-    const int q = lane >> 4, p = lane & 15;
     for (int idx = lane; idx < NT; idx += kWave) {
         // packed index -> (row, column)
         int i = 0;
         while (Tri<NC>::off(i + 1) <= idx) ++i;
         const int k = i + (idx - Tri<NC>::off(i));
-        Rs[idx] = (i < n && k < n) ? R1[i + (int64_t)k * n] : T(0);
-    }
-    T c[RPLM][NS];
-#pragma unroll
-    for (int r = 0; r < RPLM; ++r) {
-        const int i = p + 16 * r;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int k = 4 * s + q;
-            c[r][s] = (i < n && k < n && k >= i) ? R2[i + (int64_t)k * n] : T(0);
-        }
+        const bool in = i < n && k < n;
+        Rs[idx] = in ? R1[i + (int64_t)k * n] : T(0);
+        R2s[idx] = in ? R2[i + (int64_t)k * n] : T(0);
     }
     wave_sync();
-    Prefetch<T, RPLM> none{};
-    merge_chunk<T, NC, RPLM, Mode::Operator>(c, Rs, red, F, q, p, none, taus);
+    T v[NC];
+    triangle_column<T, NC>(R2s, v);
+    wave_sync();
+    merge_columns<T, NC, Mode::Operator>(v, Rs, R2s, taus);
     wave_sync();
     for (int idx = lane; idx < n * n; idx += kWave) {
         const int i = idx % n, k = idx / n;
         if (k >= i) R1[idx] = Rs[Tri<NC>::off(i) + (k - i)];
     }
 #pragma unroll
-    for (int r = 0; r < RPLM; ++r) {
-        const int i = p + 16 * r;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int k = 4 * s + q;
-            if (i < n && k < n && k >= i) R2[i + (int64_t)k * n] = c[r][s];
-        }
-    }
+    for (int i = 0; i < NC; ++i)
+        if (i <= lane && lane < n) R2[i + (int64_t)lane * n] = v[i];
     if (lane < n) tau[lane] = taus[lane];
 }
 
