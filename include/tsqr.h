@@ -60,9 +60,10 @@ extern "C" {
 
 /* options for tsqr_set_option (0 restores the automatic choice) */
 #define TSQR_OPT_LEAF_ROWS 1      /* rows per leaf block; rounded up to a whole chunk */
-#define TSQR_OPT_ROWS_PER_LANE 2  /* rows each lane holds per chunk (chunk = 64 x this); only
+#define TSQR_OPT_ROWS_PER_LANE 2  /* rows each lane holds per chunk (chunk = 16 x this rows); only
                                      compiled values take effect, others fall back */
-#define TSQR_OPT_WAVES_PER_CU 3   /* leaves per compute unit for the automatic leaf size */
+#define TSQR_OPT_WAVES_PER_CU 3   /* leaves per compute unit for the automatic leaf size
+                                     (automatic: as many as are resident on a compute unit) */
 
 typedef struct tsqr_handle_s *tsqr_handle_t;
 typedef struct tsqr_batch_plan_s *tsqr_batch_plan_t;

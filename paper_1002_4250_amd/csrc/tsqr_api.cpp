@@ -57,9 +57,24 @@ struct Geometry {
     int64_t ws_bytes = 0;
 };
 
-// Leaf policy: a chunk is 16*RPL rows; the automatic leaf size gives about
-// waves_per_cu leaves per compute unit (each leaf is one wavefront), never
-// less than one chunk.  The tree then has ceil(log2 P) levels.
+// Workgroups of the leaf kernel that fit on one compute unit at once (one
+// wavefront each): 4 for a kernel that needs more than half of a SIMD's
+// registers, 8 when two wavefronts fit per SIMD.  4 on a planning handle.
+int leaf_occupancy(const tsqr_handle_s* h, int dtype, int nc, int rpl)
+{
+    if (h->planning_only) return 4;
+    int occ = 0;
+#define TSQR_OCC(tag, NC, RPL) \
+    if ((dtype == TSQR_F64) == (sizeof(tsqr::tag) == 8) && nc == NC && rpl == RPL) occ = tsqr::occupancy_leaf_##tag##_##NC##_##RPL();
+    TSQR_LEAF_INSTANCES(TSQR_OCC)
+#undef TSQR_OCC
+    return occ > 0 ? occ : 4;
+}
+
+// Leaf policy: a chunk is 16*RPL rows; the automatic leaf size gives
+// waves_per_cu leaves per compute unit (each leaf is one wavefront; by default
+// as many as are resident at once), never less than one chunk.  The tree then
+// has ceil(log2 P) levels.
 int plan(const tsqr_handle_s* h, int64_t m, int64_t n, int dtype, Geometry* g)
 {
     g->nc = padded_columns(n);
@@ -82,7 +97,8 @@ int plan(const tsqr_handle_s* h, int64_t m, int64_t n, int dtype, Geometry* g)
     if (h->leaf_rows > 0) {
         L = align_up(h->leaf_rows, chunk);
     } else {
-        const int64_t target = (int64_t)h->cu_count * (h->waves_per_cu > 0 ? h->waves_per_cu : 4);
+        const int64_t wpc = h->waves_per_cu > 0 ? h->waves_per_cu : leaf_occupancy(h, dtype, g->nc, g->rpl);
+        const int64_t target = (int64_t)h->cu_count * wpc;
         L = (m + target - 1) / (target > 0 ? target : 1);
         L = align_up(L > chunk ? L : chunk, chunk);
     }
@@ -220,7 +236,7 @@ int tsqr_create(tsqr_handle_t* handle, int device)
     h->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     h->leaf_rows = 0;
     h->rpl = 0;
-    h->waves_per_cu = 4;
+    h->waves_per_cu = 0;
     h->last_hip_error = 0;
     h->planning_only = false;
     *handle = h;
@@ -238,7 +254,7 @@ int tsqr_create_planning(tsqr_handle_t* handle, int cu_count)
     h->cu_count = cu_count;
     h->leaf_rows = 0;
     h->rpl = 0;
-    h->waves_per_cu = 4;
+    h->waves_per_cu = 0;
     h->last_hip_error = 0;
     h->planning_only = true;
     *handle = h;

@@ -113,6 +113,13 @@ __device__ __forceinline__ T row_allreduce16(T x)
     return x;
 }
 
+// Fused multiply-add and absolute value in the element type (the generic
+// builtins would take float operands through double).
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double absv(double x) { return __builtin_fabs(x); }
+__device__ __forceinline__ float absv(float x) { return __builtin_fabsf(x); }
+
 // Value of x held by the lane whose byte address (4 * lane) is src.
 __device__ __forceinline__ double bpermute(int src, double x)
 {
@@ -172,17 +179,17 @@ __device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(
 template <typename T>
 __device__ __forceinline__ Reflector<T> make_reflector(T alpha, T sigma2)
 {
-    const T S = __builtin_fma(alpha, alpha, sigma2);
+    const T S = fmadd(alpha, alpha, sigma2);
     T y = hw_rsq(S);
     const T hS = T(0.5) * S;
 #pragma unroll
-    for (int it = 0; it < 2; ++it) y = __builtin_fma(y, __builtin_fma(-hS * y, y, T(0.5)), y);
+    for (int it = 0; it < 2; ++it) y = fmadd(y, fmadd(-hS * y, y, T(0.5)), y);
     T nrm = S * y;
-    nrm = __builtin_fma(T(0.5) * y, __builtin_fma(-nrm, nrm, S), nrm);
-    const T d = __builtin_fabs(alpha) + nrm;
+    nrm = fmadd(T(0.5) * y, fmadd(-nrm, nrm, S), nrm);
+    const T d = absv(alpha) + nrm;
     T q = hw_rcp(d);
 #pragma unroll
-    for (int it = 0; it < 2; ++it) q = __builtin_fma(q, __builtin_fma(-d, q, T(1)), q);
+    for (int it = 0; it < 2; ++it) q = fmadd(q, fmadd(-d, q, T(1)), q);
     const bool neg = __builtin_signbit(alpha);
     const bool ok = sigma2 >= Limits<T>::tiny;
     Reflector<T> r;
@@ -303,7 +310,7 @@ __device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* re
             constexpr int s = decltype(sc)::value;
             T acc = x[0] * c[0][s];
 #pragma unroll
-            for (int r = 1; r < RPL; ++r) acc = __builtin_fma(x[r], c[r][s], acc);
+            for (int r = 1; r < RPL; ++r) acc = fmadd(x[r], c[r][s], acc);
             rq[s * kRedStride + p] = acc;
         });
     }
@@ -319,7 +326,7 @@ __device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* re
     // the norm of the pivot column and its reflector
     T sp = x[0] * x[0];
 #pragma unroll
-    for (int r = 1; r < RPL; ++r) sp = __builtin_fma(x[r], x[r], sp);
+    for (int r = 1; r < RPL; ++r) sp = fmadd(x[r], x[r], sp);
     const T sigma2 = row_allreduce16(sp);
     const Reflector<T> h = make_reflector(alpha, sigma2);
 
@@ -328,8 +335,8 @@ __device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* re
         for (int hh = 8; hh >= 1; hh >>= 1)
 #pragma unroll
             for (int i = 0; i < hh; ++i) u[i] = u[i] + u[i + hh];
-        const T w = __builtin_fma(h.s, u[0], rjk);
-        Rs[ridx] = __builtin_fma(-h.tau, w, rjk);
+        const T w = fmadd(h.s, u[0], rjk);
+        Rs[ridx] = fmadd(-h.tau, w, rjk);
         F[q * 16 + p] = own ? h.ts * w : T(0);
     }
     if (q == 0 && p == 0) Rs[OFF] = h.beta;
@@ -341,7 +348,7 @@ __device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* re
             constexpr int s = decltype(sc)::value;
             const T f = F[q * 16 + s];
 #pragma unroll
-            for (int r = 0; r < RPL; ++r) c[r][s] = __builtin_fma(-f, x[r], c[r][s]);
+            for (int r = 0; r < RPL; ++r) c[r][s] = fmadd(-f, x[r], c[r][s]);
         });
     }
 
@@ -406,16 +413,16 @@ __device__ __forceinline__ void merge_columns(T (&v)[NC], T* Rs, T* xb, T* tau_o
         T d0 = x[0] * v[0], d1 = T(0);
 #pragma unroll
         for (int i = 1; i <= J; ++i) {
-            if (i & 1) d1 = __builtin_fma(x[i], v[i], d1);
-            else d0 = __builtin_fma(x[i], v[i], d0);
+            if (i & 1) d1 = fmadd(x[i], v[i], d1);
+            else d0 = fmadd(x[i], v[i], d0);
         }
         const T d = d0 + d1;
         const Reflector<T> h = make_reflector(alpha, lane_value(d, J));
-        const T w = __builtin_fma(h.s, d, rjk);
-        Rs[ridx] = __builtin_fma(-h.tau, w, rjk);
+        const T w = fmadd(h.s, d, rjk);
+        Rs[ridx] = fmadd(-h.tau, w, rjk);
         const T f = own ? h.ts * w : T(0);
 #pragma unroll
-        for (int i = 0; i <= J; ++i) v[i] = __builtin_fma(-f, x[i], v[i]);
+        for (int i = 0; i <= J; ++i) v[i] = fmadd(-f, x[i], v[i]);
         if constexpr (M == Mode::Operator) {
             const bool mine = (lane == J) && (h.tau != T(0));
 #pragma unroll

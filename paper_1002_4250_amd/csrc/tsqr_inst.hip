@@ -18,6 +18,22 @@ hipError_t TSQR_LEAF_FN2(TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL)(const LeafT
                        dim3(dev::kWave), 0, s, a);
     return hipGetLastError();
 }
+#define TSQR_OCC_FN(tag, nc, rpl) occupancy_leaf_##tag##_##nc##_##rpl
+#define TSQR_OCC_FN2(tag, nc, rpl) TSQR_OCC_FN(tag, nc, rpl)
+int TSQR_OCC_FN2(TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL)()
+{
+    // every MI355X device runs the same code object: query once per process
+    static int cached = -1;
+    if (cached < 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &n, dev::tsqr_leaf_tree_kernel<TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL>, dev::kWave, 0) !=
+            hipSuccess)
+            return 0;
+        cached = n;
+    }
+    return cached;
+}
 #define TSQR_BATCH_FN(tag, nc, rpl) launch_batch_##tag##_##nc##_##rpl
 #define TSQR_BATCH_FN2(tag, nc, rpl) TSQR_BATCH_FN(tag, nc, rpl)
 hipError_t TSQR_BATCH_FN2(TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL)(const BatchArgs<TSQR_INST_TAG>& a, int tiles,

@@ -57,15 +57,18 @@ using f32 = float;
 
 #define TSQR_DECLARE_LEAF(tag, NC, RPL) \
     hipError_t launch_leaf_tree_##tag##_##NC##_##RPL(const LeafTreeArgs<tag>& a, hipStream_t s);
+#define TSQR_DECLARE_OCC(tag, NC, RPL) int occupancy_leaf_##tag##_##NC##_##RPL();
 #define TSQR_DECLARE_BATCH(tag, NC, RPL) \
     hipError_t launch_batch_##tag##_##NC##_##RPL(const BatchArgs<tag>& a, int tiles, hipStream_t s);
 #define TSQR_DECLARE_OP(tag, NC) \
     hipError_t launch_qr_uppers_##tag##_##NC(int n, tag* R1, tag* R2, tag* tau, hipStream_t s);
 TSQR_LEAF_INSTANCES(TSQR_DECLARE_LEAF)
 TSQR_LEAF_INSTANCES(TSQR_DECLARE_BATCH)
+TSQR_LEAF_INSTANCES(TSQR_DECLARE_OCC)
 TSQR_OP_INSTANCES(TSQR_DECLARE_OP)
 #undef TSQR_DECLARE_LEAF
 #undef TSQR_DECLARE_BATCH
+#undef TSQR_DECLARE_OCC
 #undef TSQR_DECLARE_OP
 
 hipError_t launch_zero_u32(unsigned* p, int64_t count, hipStream_t s);
