@@ -4,10 +4,14 @@
 Workload (the paper's problem at production size): one instance of
 m = 2^22 rows by n = 50 columns, FP64, entries uniform[-1,1) from seed 1,
 resident in HBM before timing starts.  A step is one full pass of the hot path
-(leaf factorisations + reduction tree + finalisation: one kernel launch through
-the C ABI).  Prints ONE JSON line on stdout; progress goes to stderr.
+(leaf factorisations + reduction tree + finalisation) through one C-ABI call,
+which launches a small kernel that clears the tree counters and then the fused
+leaf+tree kernel.  Prints ONE JSON line on stdout; progress goes to stderr.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline] [--no-batched]
+    python bench.py [--gpus 1] [--steps 50] [--warmup 30] [--no-cpu-baseline] [--no-batched]
+
+The warmup is long enough (about 50 ms of kernel time) for the GPU clocks to
+settle before the timed steps.
 
 The ``batched`` object of the line measures the ragged batch (4096 instances,
 m log-uniform in [64, 65536], n = 50, FP32) three ways: one batched launch per
@@ -104,8 +108,8 @@ def time_batched(torch, tsqr, inputs, steps, warmup, n=50, count=4096):
     tiles, leaves, L = plan.info()
     R = torch.empty((count, n, n), dtype=torch.float32, device="cuda")
 
-    def timed(fn, k):
-        for _ in range(warmup):
+    def timed(fn, k, w):
+        for _ in range(w):
             fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -116,7 +120,7 @@ def time_batched(torch, tsqr, inputs, steps, warmup, n=50, count=4096):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / k
 
-    ms_batched = timed(lambda: plan.run(Ad, R), steps)
+    ms_batched = timed(lambda: plan.run(Ad, R), steps, warmup)
     Rb = R.clone()
 
     # looped single-matrix calls over the same device data, one shared workspace
@@ -132,7 +136,7 @@ def time_batched(torch, tsqr, inputs, steps, warmup, n=50, count=4096):
             tsqr.geqr_r(views[b], R=outs[b], ws=ws, h=h)
 
     loop_steps = max(1, min(steps, 3))
-    ms_loop = timed(loop, loop_steps)
+    ms_loop = timed(loop, loop_steps, 1)
     same_as_loop = None
     # the same loop captured once in a HIP graph (no per-call host overhead)
     ms_graph = None
@@ -146,7 +150,7 @@ def time_batched(torch, tsqr, inputs, steps, warmup, n=50, count=4096):
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             loop()
-        ms_graph = timed(g.replay, steps)
+        ms_graph = timed(g.replay, loop_steps, 1)
     except RuntimeError as e:
         log(f"graph capture of the loop failed: {e}")
     torch.cuda.synchronize()
@@ -166,7 +170,7 @@ def time_batched(torch, tsqr, inputs, steps, warmup, n=50, count=4096):
         "tiles": tiles, "leaf_rows": L,
         "plain_loop": {"value": count / (ms_loop * 1e-3), "ms_per_step": ms_loop, "steps": loop_steps},
         "plain_loop_graph": None if ms_graph is None else
-        {"value": count / (ms_graph * 1e-3), "ms_per_step": ms_graph},
+        {"value": count / (ms_graph * 1e-3), "ms_per_step": ms_graph, "steps": loop_steps},
         "speedup_vs_loop": ms_loop / ms_batched,
         "speedup_vs_graph_loop": None if ms_graph is None else ms_graph / ms_batched,
         "rel_diff_vs_plain_calls": same_as_loop,
@@ -181,8 +185,8 @@ def time_batched(torch, tsqr, inputs, steps, warmup, n=50, count=4096):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--m", type=int, default=1 << 22)

@@ -156,7 +156,7 @@ int tsqr_qr_uppers_f32(tsqr_handle_t handle, int64_t n, float *R1, float *R2, fl
  * the m[b]-by-n column-major matrix at element offset a_offset[b] of the A
  * pointer given to tsqr_batch_exec, with leading dimension lda[b] (NULL:
  * lda[b] = max(1, m[b])).  The leaf size is the handle's TSQR_OPT_LEAF_ROWS if
- * set, else 32 chunks.  The plan allocates two small device tables (freed by
+ * set, else 64 chunks.  The plan allocates two small device tables (freed by
  * tsqr_batch_plan_destroy) and keeps a pointer to the handle, which must
  * outlive it.  Argument codes: -1 handle, -2 batch, -3 n, -4 m, -5 a_offset,
  * -6 lda, -7 dtype, -8 plan. */

@@ -383,9 +383,11 @@ int tsqr_batch_plan_create(tsqr_handle_t h, int64_t batch, int64_t n, const int6
     int rc = n > 0 ? plan(h, 1, n, dtype, &g) : 0;
     if (rc) return rc;
     const int64_t chunk = (int64_t)kRowsPerLaneUnit * (n > 0 ? g.rpl : 1);
-    // batched leaves: the handle's leaf size if set, else 32 chunks (long
-    // enough that streaming dominates, short enough to split big instances)
-    const int64_t L = h->leaf_rows > 0 ? align_up(h->leaf_rows, chunk) : 32 * chunk;
+    // batched leaves: the handle's leaf size if set, else 64 chunks (8192
+    // rows at 8 rows per lane).  Leaves that long keep most instances of a
+    // ragged batch in a single leaf, with no tree at all, and give the large
+    // ones shallow trees; the many instances supply the parallelism.
+    const int64_t L = h->leaf_rows > 0 ? align_up(h->leaf_rows, chunk) : 64 * chunk;
     std::vector<tsqr::BatchInstance> inst((size_t)batch);
     std::vector<tsqr::BatchTile> tiles;
     std::vector<int64_t> tile_rows;

@@ -145,7 +145,7 @@ def test_batch_plan_tiles_and_workspace(ph):
     p = _batch_create(ph, sizes, 50)
     try:
         tiles, leaves, L = tsqr.tsqr_batch_plan_info(p)
-        assert L == 32 * 16 * 8
+        assert L == 64 * 16 * 8
         want = sum(max(1, -(-m // L)) for m in sizes)
         assert tiles == leaves == want
         tri = 50 * 51 // 2
@@ -212,7 +212,7 @@ def test_batch_plan_empty(ph):
     import numpy as np
     p = tsqr.tsqr_batch_plan_create(ph, 0, 50, np.zeros(0, np.int64), np.zeros(0, np.int64), None, 0)
     try:
-        assert tsqr.tsqr_batch_plan_info(p) == (0, 0, 32 * 16 * 8)
+        assert tsqr.tsqr_batch_plan_info(p) == (0, 0, 64 * 16 * 8)
         # nothing to do: succeeds without touching any pointer
         assert tsqr.lib().tsqr_batch_exec(p, None, None, 50, None, 0, None) == 0
     finally:
