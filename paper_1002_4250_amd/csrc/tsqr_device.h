@@ -378,10 +378,11 @@ __device__ __forceinline__ void merge_chunk(T (&c)[RPL][Slots<NC>::NS], T* Rs, T
 // in the structured form of Table 3 (only rows 0..J of R2 take part in step J).
 // R1 is packed by rows in LDS (Rs, with one spare cell after it); lane k holds
 // column k of R2 in registers (v[i] = R2(i, k), zero below the diagonal).  In
-// step J the pivot lane J publishes R2(0:J, J) through LDS; every lane then
-// forms its own dot product with it locally (lane J's is sigma^2, read by all
-// lanes from its register), so a step has a single LDS round trip and no
-// cross-lane reduction, and lane k > J updates R1(J, k) and its column.  Used by the reduction tree and the operator entry point,
+// step J every lane fetches the pivot column R2(0:J, J) from lane J's
+// registers (ds_bpermute) and forms its own dot product with it locally
+// (lane J's is sigma^2, which all lanes then read from its register), so a
+// step has no cross-lane reduction, and lane k > J updates R1(J, k) and its
+// column.  Used by the reduction tree and the operator entry point,
 // where the operands have only NC rows and the length of the dependent chain
 // of NC steps, not the arithmetic, sets the time.
 //
@@ -390,7 +391,7 @@ __device__ __forceinline__ void merge_chunk(T (&c)[RPL][Slots<NC>::NS], T* Rs, T
 enum class Mode { Merge, Operator };
 
 template <typename T, int NC, Mode M>
-__device__ __forceinline__ void merge_columns(T (&v)[NC], T* Rs, T* xb, T* tau_out)
+__device__ __forceinline__ void merge_columns(T (&v)[NC], T* Rs, T* tau_out)
 {
     const int lane = threadIdx.x;
     static_for<0, NC>([&](auto jc) {
@@ -400,14 +401,10 @@ __device__ __forceinline__ void merge_columns(T (&v)[NC], T* Rs, T* xb, T* tau_o
         const int ridx = own ? OFF + lane - J : Tri<NC>::kSize;
         const T alpha = Rs[OFF];
         const T rjk = Rs[ridx];
-        if (lane == J) {
-#pragma unroll
-            for (int i = 0; i <= J; ++i) xb[i] = v[i];
-        }
-        lds_order();
+        // the pivot column, from lane J's registers to every lane
         T x[J + 1];
 #pragma unroll
-        for (int i = 0; i <= J; ++i) x[i] = xb[i];
+        for (int i = 0; i <= J; ++i) x[i] = bpermute(J << 2, v[i]);
         // this lane's dot product with the pivot column (two accumulators);
         // for lane J it is sigma^2 itself
         T d0 = x[0] * v[0], d1 = T(0);
@@ -553,7 +550,7 @@ __device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T>& a, int lea
             triangle_to_lds<T, NC>(a.tri + (int64_t)partner * NT, Rs);
         }
         wave_sync();
-        merge_columns<T, NC, Mode::Merge>(v, Rs, red, nullptr);
+        merge_columns<T, NC, Mode::Merge>(v, Rs, nullptr);
         wave_sync();
         node = left;
         ++level;
@@ -649,7 +646,7 @@ __global__ void __launch_bounds__(kWave) qr_uppers_kernel(int n, T* R1, T* R2, T
     T v[NC];
     triangle_column<T, NC>(R2s, v);
     wave_sync();
-    merge_columns<T, NC, Mode::Operator>(v, Rs, R2s, taus);
+    merge_columns<T, NC, Mode::Operator>(v, Rs, taus);
     wave_sync();
     for (int idx = lane; idx < n * n; idx += kWave) {
         const int i = idx % n, k = idx / n;
