@@ -275,7 +275,7 @@ __device__ __forceinline__ void prefetch_slot(T (&c)[RPL][NS], int slot, Prefetc
 // NC steps of a chunk are unrolled at compile time so every register index is
 // static and the scheduler can overlap consecutive steps.
 template <typename T, int NC, int RPL, int J>
-__device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* red, T* F, int q, int p,
+__device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* red, int q, int p,
                                         int kcol, int spare, Prefetch<T, RPL>& pf)
 {
     constexpr int NS = Slots<NC>::NS;
@@ -317,6 +317,7 @@ __device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* re
     lds_order();
     // (c) lane (q, p) gathers the 16 partials of column k = 4p + q
     T u[16];
+    T fown = T(0);
     if constexpr (K > 0) {
         const T* rd = rq + p * kRedStride;
 #pragma unroll
@@ -337,16 +338,18 @@ __device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* re
             for (int i = 0; i < hh; ++i) u[i] = u[i] + u[i + hh];
         const T w = fmadd(h.s, u[0], rjk);
         Rs[ridx] = fmadd(-h.tau, w, rjk);
-        F[q * 16 + p] = own ? h.ts * w : T(0);
+        fown = own ? h.ts * w : T(0);
     }
     if (q == 0 && p == 0) Rs[OFF] = h.beta;
     lds_order();
 
     if constexpr (K > 0) {
-        // (d) rank-1 update of the live slots
+        // (d) rank-1 update of the live slots; the coefficient of slot s (column
+        // 4s + q) is held by lane s of the lane row and reaches the other 15
+        // lanes by a row broadcast (DPP row_newbcast), not through LDS
         static_for<SJ, NS>([&](auto sc) {
             constexpr int s = decltype(sc)::value;
-            const T f = F[q * 16 + s];
+            const T f = dpp_mov<0x150 + s>(fown);
 #pragma unroll
             for (int r = 0; r < RPL; ++r) c[r][s] = fmadd(-f, x[r], c[r][s]);
         });
@@ -358,7 +361,7 @@ __device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* re
 }
 
 template <typename T, int NC, int RPL>
-__device__ __forceinline__ void merge_chunk(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* red, T* F, int q, int p,
+__device__ __forceinline__ void merge_chunk(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* red, int q, int p,
                                             Prefetch<T, RPL>& pf)
 {
     // the column a lane completes in the reduction, passed through an opaque
@@ -368,7 +371,7 @@ __device__ __forceinline__ void merge_chunk(T (&c)[RPL][Slots<NC>::NS], T* Rs, T
     asm volatile("" : "+v"(kcol));
     const int spare = Tri<NC>::kSize;      // one LDS cell past the triangle
     static_for<0, NC>([&](auto jc) {
-        hh_step<T, NC, RPL, decltype(jc)::value>(c, Rs, red, F, q, p, kcol, spare, pf);
+        hh_step<T, NC, RPL, decltype(jc)::value>(c, Rs, red, q, p, kcol, spare, pf);
     });
 }
 
@@ -473,7 +476,7 @@ __device__ __forceinline__ void triangle_to_lds(const T* __restrict__ src, T* ds
 // instance (its matrix, leaf size and count, triangle slots, tree counters and
 // output); `leaf` is this workgroup's leaf.
 template <typename T, int NC, int RPL>
-__device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T>& a, int leaf, T* Rs, T* red, T* F)
+__device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T>& a, int leaf, T* Rs, T* red)
 {
     constexpr int CH = 16 * RPL;                  // rows per chunk
     constexpr int NT = Tri<NC>::kSize;
@@ -504,7 +507,7 @@ __device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T>& a, int lea
         const int64_t nchunks = (r1 - r0 + CH - 1) / CH;
         for (int64_t t = 0; t < nchunks; ++t) {
             Prefetch<T, RPL> pf = make_prefetch<T, RPL>(a.A, a.lda, a.n, r0 + (t + 1) * CH, r1, q, p);
-            merge_chunk<T, NC, RPL>(c, Rs, red, F, q, p, pf);
+            merge_chunk<T, NC, RPL>(c, Rs, red, q, p, pf);
         }
     }
     wave_sync();
@@ -592,8 +595,7 @@ __global__ void __launch_bounds__(kWave) tsqr_leaf_tree_kernel(LeafTreeArgs<T> a
 {
     __shared__ T Rs[Tri<NC>::kPadded];
     __shared__ T red[LdsScratch<NC>::kElems];
-    __shared__ T F[kWave];
-    leaf_tree_body<T, NC, RPL>(a, xcd_local_leaf(blockIdx.x, a.leaves), Rs, red, F);
+    leaf_tree_body<T, NC, RPL>(a, xcd_local_leaf(blockIdx.x, a.leaves), Rs, red);
 }
 
 // Many independent instances in one launch: workgroup g takes tile
@@ -606,7 +608,6 @@ __global__ void __launch_bounds__(kWave) tsqr_batch_kernel(BatchArgs<T> b)
 {
     __shared__ T Rs[Tri<NC>::kPadded];
     __shared__ T red[LdsScratch<NC>::kElems];
-    __shared__ T F[kWave];
     const BatchTile t = b.tiles[blockIdx.x];
     const BatchInstance in = b.inst[t.inst];
     LeafTreeArgs<T> a;
@@ -620,7 +621,7 @@ __global__ void __launch_bounds__(kWave) tsqr_batch_kernel(BatchArgs<T> b)
     a.tickets = b.tickets + in.ticket_off;
     a.R = b.R + (int64_t)t.inst * b.ldr * b.n;
     a.ldr = b.ldr;
-    leaf_tree_body<T, NC, RPL>(a, t.leaf, Rs, red, F);
+    leaf_tree_body<T, NC, RPL>(a, t.leaf, Rs, red);
 }
 
 // ---- the paper's operator as a single-workgroup kernel -------------------------
