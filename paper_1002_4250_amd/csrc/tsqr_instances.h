@@ -6,7 +6,7 @@
 #pragma once
 
 #define TSQR_LEAF_INSTANCES(X) \
-    X(f64, 16, 8) X(f64, 32, 8) X(f64, 50, 4) X(f64, 50, 6) X(f64, 50, 8) X(f64, 50, 10) X(f64, 64, 8) \
+    X(f64, 16, 8) X(f64, 32, 8) X(f64, 50, 4) X(f64, 50, 6) X(f64, 50, 8) X(f64, 64, 8) \
     X(f32, 16, 8) X(f32, 32, 8) X(f32, 50, 8) X(f32, 50, 12) X(f32, 50, 16) X(f32, 64, 8)
 
 #define TSQR_OP_INSTANCES(O) \
