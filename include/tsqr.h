@@ -67,6 +67,7 @@ extern "C" {
 
 typedef struct tsqr_handle_s *tsqr_handle_t;
 typedef struct tsqr_batch_plan_s *tsqr_batch_plan_t;
+typedef struct tsqr_mixed_plan_s *tsqr_mixed_plan_t;
 
 /* Create a handle bound to HIP device `device` (which becomes current on the
  * calling thread).  Reads the device's compute-unit count for the launch
@@ -178,6 +179,33 @@ int tsqr_batch_plan_info(tsqr_batch_plan_t plan, int64_t *tiles, int64_t *leaves
  * Argument codes: -1 plan, -2 A, -3 R, -4 ldr, -5 ws, -6 ws_bytes. */
 int tsqr_batch_exec(tsqr_batch_plan_t plan, const void *A, void *R, int64_t ldr, void *ws, int64_t ws_bytes,
                     void *stream);
+
+/* ---- mixed precision: FP32 TSQR, then one FP64 correction -------------------
+ *
+ * For `batch` matrices of equal shape m x n stored in FP32 (instance b at
+ * A + b*stride_a, column-major, leading dimension lda), R with FP64 accuracy:
+ * the FP32 batched TSQR (section 2 of the paper in FP32) gives R~; one FP64
+ * pass over A then forms Y = A R~^-1 and G = Y^T Y and returns
+ * R = chol(G) R~, the second pass of CholeskyQR2 (Fukaya, Nakatsukasa,
+ * Yanagisawa, Yamamoto 2014) with the Householder factorization as its first
+ * pass.  It is accurate while kappa(A) * 2^-24 << 1.  An instance whose G is
+ * not numerically positive definite (roughly kappa(A) > 1e7) is refactored
+ * with the plain FP64 TSQR path from its FP32 storage and reported in
+ * `fallback`.
+ *
+ * Create: argument codes -1 handle, -2 batch, -3 m, -4 n, -5 lda, -6 stride_a,
+ * -7 plan; the plan holds a batched FP32 plan (two small device tables).
+ * Exec: R is FP64, instance b's n x n R (diag >= 0) at R + b*ldr*n;
+ * `fallback` is NULL or a HOST array of `batch` ints (1 = the instance took
+ * the FP64 path).  The call synchronizes `stream` once to read the Cholesky
+ * flags, so it cannot be captured in a graph.  Argument codes -1 plan, -2 A,
+ * -3 R, -4 ldr, -6 ws, -7 ws_bytes. */
+int tsqr_mixed_plan_create(tsqr_handle_t handle, int64_t batch, int64_t m, int64_t n, int64_t lda,
+                           int64_t stride_a, tsqr_mixed_plan_t *plan);
+int tsqr_mixed_plan_destroy(tsqr_mixed_plan_t plan);
+int64_t tsqr_mixed_workspace_bytes(tsqr_mixed_plan_t plan);
+int tsqr_mixed_exec(tsqr_mixed_plan_t plan, const float *A, double *R, int64_t ldr, int *fallback, void *ws,
+                    int64_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -49,8 +49,8 @@ def instances():
     return units
 
 
-KERNEL_DEPS = ["tsqr_inst.hip", "tsqr_device.h", "tsqr_internal.h", "tsqr_instances.h"]
-API_DEPS = ["tsqr_api.cpp", "tsqr_internal.h", "tsqr_instances.h"]
+KERNEL_DEPS = ["tsqr_inst.hip", "tsqr_device.h", "tsqr_mixed.h", "tsqr_internal.h", "tsqr_instances.h"]
+API_DEPS = ["tsqr_api.cpp", "tsqr_internal.h", "tsqr_instances.h", "tsqr_mixed.h", "tsqr_device.h"]
 
 
 def _digest(names):

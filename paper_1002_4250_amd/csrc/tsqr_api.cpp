@@ -518,4 +518,174 @@ int tsqr_batch_exec(tsqr_batch_plan_t plan, const void* A, void* R, int64_t ldr,
     return hip_status(plan->h, e);
 }
 
+// ---- mixed precision: FP32 TSQR, then one FP64 correction --------------------
+
+struct tsqr_mixed_plan_s {
+    tsqr_handle_s* h;
+    int64_t batch, m, n, lda, stride_a;
+    int nc;
+    tsqr_batch_plan_t inner;     // the FP32 batched factorization
+    int64_t rows_per_block;
+    int blocks;
+    int64_t off_inner, inner_bytes, off_rt, off_part, off_flags, off_a64, off_ws64, ws64_bytes, ws_bytes;
+};
+
+namespace {
+constexpr int64_t kMixedRowsPerBlock = 4096;
+
+hipError_t dispatch_mixed(const tsqr::MixedArgs& a, int nc, int batch, hipStream_t s)
+{
+    switch (nc) {
+    case 16: return tsqr::launch_mixed_16(a, batch, s);
+    case 32: return tsqr::launch_mixed_32(a, batch, s);
+    case 50: return tsqr::launch_mixed_50(a, batch, s);
+    case 64: return tsqr::launch_mixed_64(a, batch, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int gram_width(int nc)
+{
+    switch (nc) {
+    case 16: return tsqr::GramTile<16>::W;
+    case 32: return tsqr::GramTile<32>::W;
+    case 50: return tsqr::GramTile<50>::W;
+    default: return tsqr::GramTile<64>::W;
+    }
+}
+}  // namespace
+
+int tsqr_mixed_plan_create(tsqr_handle_t h, int64_t batch, int64_t m, int64_t n, int64_t lda, int64_t stride_a,
+                           tsqr_mixed_plan_t* out)
+{
+    if (!h) return -1;
+    if (batch < 0) return -2;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (lda < (m > 1 ? m : 1)) return -5;
+    if (batch > 1 && stride_a < lda * n) return -6;
+    if (stride_a < 0) return -6;
+    if (!out) return -7;
+    *out = nullptr;
+    if (n > TSQR_MAX_N) return TSQR_ERR_UNSUPPORTED;
+    const int nc = n > 0 ? padded_columns(n) : 16;
+    if (nc < 0) return TSQR_ERR_UNSUPPORTED;
+    std::vector<int64_t> ms((size_t)batch, m), offs((size_t)batch), ldas((size_t)batch, lda);
+    for (int64_t b = 0; b < batch; ++b) offs[(size_t)b] = b * stride_a;
+    tsqr_batch_plan_t inner = nullptr;
+    int rc = tsqr_batch_plan_create(h, batch, n, ms.data(), offs.data(), ldas.data(), TSQR_F32, &inner);
+    if (rc) return rc;
+    tsqr_mixed_plan_s* p = new (std::nothrow) tsqr_mixed_plan_s;
+    if (!p) {
+        tsqr_batch_plan_destroy(inner);
+        return TSQR_ERR_ALLOC;
+    }
+    p->h = h;
+    p->batch = batch;
+    p->m = m;
+    p->n = n;
+    p->lda = lda;
+    p->stride_a = stride_a;
+    p->nc = nc;
+    p->inner = inner;
+    p->rows_per_block = kMixedRowsPerBlock;
+    p->blocks = (int)(m > 0 ? (m + kMixedRowsPerBlock - 1) / kMixedRowsPerBlock : 1);
+    const int64_t W = gram_width(nc);
+    Geometry g64;
+    const int64_t ws64 = (n > 0 && plan(h, m, n, TSQR_F64, &g64) == 0) ? g64.ws_bytes : 0;
+    p->inner_bytes = tsqr_batch_workspace_bytes(inner);
+    int64_t off = 0;
+    p->off_inner = off;
+    off += align_up(p->inner_bytes > 0 ? p->inner_bytes : 0, kAlign);
+    p->off_rt = off;
+    off += align_up(batch * n * n * 4, kAlign);
+    p->off_part = off;
+    off += align_up(batch * p->blocks * W * W * 8, kAlign);
+    p->off_flags = off;
+    off += align_up(batch * 4, kAlign);
+    p->off_a64 = off;
+    off += align_up(m * n * 8, kAlign);
+    p->off_ws64 = off;
+    p->ws64_bytes = ws64;
+    off += align_up(ws64, kAlign);
+    p->ws_bytes = off;
+    *out = p;
+    return 0;
+}
+
+int tsqr_mixed_plan_destroy(tsqr_mixed_plan_t plan)
+{
+    if (!plan) return 0;
+    tsqr_batch_plan_destroy(plan->inner);
+    delete plan;
+    return 0;
+}
+
+int64_t tsqr_mixed_workspace_bytes(tsqr_mixed_plan_t plan)
+{
+    if (!plan) return -1;
+    return plan->ws_bytes;
+}
+
+int tsqr_mixed_exec(tsqr_mixed_plan_t plan, const float* A, double* R, int64_t ldr, int* fallback, void* ws,
+                    int64_t ws_bytes, void* stream)
+{
+    if (!plan) return -1;
+    const bool work = plan->batch > 0 && plan->n > 0;
+    if (work && plan->m > 0 && !A) return -2;
+    if (work && !R) return -3;
+    if (ldr < (plan->n > 1 ? plan->n : 1)) return -4;
+    if (!work) return 0;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) != 0) return -6;
+    if (ws_bytes < plan->ws_bytes) return -7;
+    if (plan->h->planning_only) return TSQR_ERR_NO_DEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(ws);
+    float* Rt = reinterpret_cast<float*>(base + plan->off_rt);
+    int rc = 0;
+    if (plan->m > 0) {
+        rc = tsqr_batch_exec(plan->inner, A, Rt, plan->n, base + plan->off_inner, plan->inner_bytes, stream);
+        if (rc) return rc;
+    }
+    tsqr::MixedArgs a;
+    a.A = A;
+    a.m = plan->m;
+    a.lda = plan->lda;
+    a.stride_a = plan->stride_a;
+    a.n = (int)plan->n;
+    a.Rt = Rt;
+    a.part = reinterpret_cast<double*>(base + plan->off_part);
+    a.rows_per_block = plan->rows_per_block;
+    a.blocks = plan->blocks;
+    a.R = R;
+    a.ldr = ldr;
+    a.flags = reinterpret_cast<int*>(base + plan->off_flags);
+    if (plan->m > 0) {
+        hipError_t e = dispatch_mixed(a, plan->nc, (int)plan->batch, s);
+        if (e != hipSuccess) return hip_status(plan->h, e);
+    }
+    // read the flags (one synchronization) and refactor the failed instances
+    // in FP64 from their FP32 storage
+    std::vector<int> flags((size_t)plan->batch, 1);
+    if (plan->m > 0) {
+        hipError_t e = hipMemcpyAsync(flags.data(), a.flags, sizeof(int) * flags.size(), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_status(plan->h, e);
+    }
+    double* a64 = reinterpret_cast<double*>(base + plan->off_a64);
+    const int64_t ld64 = plan->m > 1 ? plan->m : 1;
+    for (int64_t b = 0; b < plan->batch; ++b) {
+        if (!flags[(size_t)b]) continue;
+        hipError_t e = tsqr::launch_convert_f32_f64(A ? A + b * plan->stride_a : nullptr, plan->m, plan->n,
+                                                   plan->lda, a64, s);
+        if (e != hipSuccess) return hip_status(plan->h, e);
+        rc = tsqr_geqr_r_f64(plan->h, plan->m, plan->n, a64, ld64, R + b * ldr * plan->n, ldr,
+                             base + plan->off_ws64, plan->ws64_bytes, stream);
+        if (rc) return rc;
+    }
+    if (fallback)
+        for (int64_t b = 0; b < plan->batch; ++b) fallback[b] = flags[(size_t)b];
+    return 0;
+}
+
 }  // extern "C"

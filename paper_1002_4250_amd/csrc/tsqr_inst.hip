@@ -4,6 +4,7 @@
 // kernel, or -DTSQR_INST_COMMON for the small helper kernels.
 #include "tsqr_device.h"
 #include "tsqr_internal.h"
+#include "tsqr_mixed.h"
 
 
 namespace tsqr {
@@ -54,14 +55,53 @@ hipError_t TSQR_OP_FN2(TSQR_INST_TAG, TSQR_INST_NC)(int n, TSQR_INST_TAG* R1, TS
                        R1, R2, tau);
     return hipGetLastError();
 }
+// the FP64 correction kernels exist once per column count (with the f64 tag)
+#define TSQR_MIXED_FN(nc) launch_mixed_##nc
+#define TSQR_MIXED_FN2(nc) TSQR_MIXED_FN(nc)
+#define TSQR_IS_F64_f64 1
+#define TSQR_IS_F64_f32 0
+#define TSQR_IS_F64_(tag) TSQR_IS_F64_##tag
+#define TSQR_IS_F64(tag) TSQR_IS_F64_(tag)
+#if TSQR_IS_F64(TSQR_INST_TAG)
+hipError_t TSQR_MIXED_FN2(TSQR_INST_NC)(const MixedArgs& a, int batch, hipStream_t s)
+{
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL((dev::mixed_gram_kernel<TSQR_INST_NC>), dim3(a.blocks, batch), dim3(dev::kWave), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((dev::mixed_finish_kernel<TSQR_INST_NC>), dim3(batch), dim3(dev::kWave), 0, s, a);
+    return hipGetLastError();
+}
+#endif
 #elif defined(TSQR_INST_COMMON)
 namespace dev {
+// FP32 column-major matrix to FP64 with leading dimension m (fallback input)
+__global__ void convert_f32_f64_kernel(const float* A, int64_t m, int64_t n, int64_t lda, double* out)
+{
+    const int64_t total = m * n;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
+        const int64_t i = idx % m, j = idx / m;
+        out[idx] = (double)A[i + j * lda];
+    }
+}
+
 __global__ void zero_u32_kernel(unsigned* p, int64_t count)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0u;
 }
 }  // namespace dev
+
+hipError_t launch_convert_f32_f64(const float* A, int64_t m, int64_t n, int64_t lda, double* out, hipStream_t s)
+{
+    const int64_t total = m * n;
+    if (total <= 0) return hipSuccess;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(dev::convert_f32_f64_kernel, dim3((unsigned)blocks), dim3(256), 0, s, A, m, n, lda, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_zero_u32(unsigned* p, int64_t count, hipStream_t s)
 {

@@ -72,5 +72,38 @@ TSQR_OP_INSTANCES(TSQR_DECLARE_OP)
 #undef TSQR_DECLARE_OP
 
 hipError_t launch_zero_u32(unsigned* p, int64_t count, hipStream_t s);
+hipError_t launch_convert_f32_f64(const float* A, int64_t m, int64_t n, int64_t lda, double* out, hipStream_t s);
+
+// Register blocking of G: a 10 x 10 grid of S x S blocks covers the padded
+// width W = 10 S >= NC; the 55 blocks on or above the diagonal go to lanes
+// 0..54.
+template <int NC>
+struct GramTile {
+    static constexpr int S = (NC + 9) / 10;
+    static constexpr int W = 10 * S;
+    static constexpr int kBlocks = 55;
+};
+
+struct MixedArgs {
+    const float* A;        // instance b at A + b * stride_a, column-major, lda
+    int64_t m;
+    int64_t lda;
+    int64_t stride_a;
+    int n;
+    const float* Rt;       // R~ of instance b at Rt + b * n * n, column-major, ld n
+    double* part;          // per (instance, row block): W x W partial Gram sums
+    int64_t rows_per_block;
+    int blocks;            // row blocks per instance
+    double* R;             // instance b's R at R + b * ldr * n
+    int64_t ldr;
+    int* flags;            // per instance: 0 corrected, 1 Cholesky failed
+};
+
+#define TSQR_DECLARE_MIXED(NC) hipError_t launch_mixed_##NC(const MixedArgs& a, int batch, hipStream_t s);
+TSQR_DECLARE_MIXED(16)
+TSQR_DECLARE_MIXED(32)
+TSQR_DECLARE_MIXED(50)
+TSQR_DECLARE_MIXED(64)
+#undef TSQR_DECLARE_MIXED
 
 }  // namespace tsqr

@@ -111,3 +111,29 @@ def instance(flat: np.ndarray, sizes, offsets, b: int, n: int) -> np.ndarray:
     m = int(sizes[b])
     o = int(offsets[b])
     return flat[o:o + m * n].reshape(n, m).T
+
+
+def conditioned(m: int, n: int, kappa: float, seed: int, dtype=np.float32) -> np.ndarray:
+    """A = U diag(sigma) V^T with singular values sigma_j = kappa^(-j/(n-1))
+    (so cond_2(A) = kappa before rounding), U (m x n) and V (n x n) the
+    orthonormal factors of uniform[-1, 1) draws from ``default_rng(seed)``,
+    formed in FP64 and rounded to ``dtype``.  Column-major."""
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.uniform(-1.0, 1.0, size=(m, n)))
+    V, _ = np.linalg.qr(rng.uniform(-1.0, 1.0, size=(n, n)))
+    sigma = kappa ** (-np.arange(n) / max(n - 1, 1))
+    A = (U * sigma[None, :]) @ V.T
+    return np.asfortranarray(A.astype(dtype))
+
+
+def conditioned_batch(batch: int, m: int, n: int, log10_kappa_max: float = 8.0, seed: int = 3,
+                      dtype=np.float32):
+    """Instances i = 0..batch-1 of :func:`conditioned` with
+    kappa_i = 10^(log10_kappa_max * i / (batch - 1)) and seed (seed, i),
+    stacked with stride m*n in one flat array.  Returns (flat, kappas)."""
+    kappas = 10.0 ** (log10_kappa_max * np.arange(batch) / max(batch - 1, 1))
+    flat = np.empty(batch * m * n, dtype=dtype)
+    for i in range(batch):
+        A = conditioned(m, n, float(kappas[i]), seed=[seed, i], dtype=dtype)
+        flat[i * m * n:(i + 1) * m * n] = A.T.ravel()
+    return flat, kappas

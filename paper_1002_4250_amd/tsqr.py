@@ -48,6 +48,10 @@ SIGNATURES = [
     ("tsqr_batch_workspace_bytes", _i64, [_p]),
     ("tsqr_batch_plan_info", _i, [_p, _pi64, _pi64, _pi64]),
     ("tsqr_batch_exec", _i, [_p, _p, _p, _i64, _p, _i64, _p]),
+    ("tsqr_mixed_plan_create", _i, [_p, _i64, _i64, _i64, _i64, _i64, ctypes.POINTER(_p)]),
+    ("tsqr_mixed_plan_destroy", _i, [_p]),
+    ("tsqr_mixed_workspace_bytes", _i64, [_p]),
+    ("tsqr_mixed_exec", _i, [_p, _p, _p, _i64, ctypes.POINTER(ctypes.c_int), _p, _i64, _p]),
 ]
 
 _LOCK = threading.Lock()
@@ -302,6 +306,70 @@ class BatchPlan:
         try:
             if getattr(self, "plan", None):
                 tsqr_batch_plan_destroy(self.plan)
+                self.plan = None
+        except Exception:
+            pass
+
+
+# ---- mixed precision ------------------------------------------------------------
+
+def tsqr_mixed_plan_create(handle, batch, m, n, lda, stride_a) -> int:
+    plan = ctypes.c_void_p()
+    st = lib().tsqr_mixed_plan_create(handle, int(batch), int(m), int(n), int(lda), int(stride_a), ctypes.byref(plan))
+    _check("tsqr_mixed_plan_create", st, handle)
+    return plan.value
+
+
+def tsqr_mixed_plan_destroy(plan) -> None:
+    lib().tsqr_mixed_plan_destroy(plan)
+
+
+def tsqr_mixed_workspace_bytes(plan) -> int:
+    v = lib().tsqr_mixed_workspace_bytes(plan)
+    if v < 0:
+        raise TsqrError("tsqr_mixed_workspace_bytes", int(v))
+    return int(v)
+
+
+def tsqr_mixed_exec(plan, A, R, ldr, fallback, ws, ws_bytes, stream) -> int:
+    return lib().tsqr_mixed_exec(plan, A, R, ldr, fallback, ws, ws_bytes, stream)
+
+
+class MixedPlan:
+    """FP64-accurate R of `batch` FP32-stored m x n matrices held in one flat
+    device tensor (instance b at element offset b * stride).  ``run(A)``
+    returns (R, fallback): R a (batch, n, n) float64 tensor whose [b] is
+    instance b's R stored column-major, fallback a list of 0/1 per instance
+    (1: refactored by the FP64 path)."""
+
+    def __init__(self, batch, m, n, stride=None, lda=None, device=None, h=None):
+        import torch
+        self.torch = torch
+        self.dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.h = h or handle(self.dev.index or 0)
+        self.batch, self.m, self.n = int(batch), int(m), int(n)
+        lda = max(self.m, 1) if lda is None else int(lda)
+        stride = lda * self.n if stride is None else int(stride)
+        self.plan = tsqr_mixed_plan_create(self.h, self.batch, self.m, self.n, lda, stride)
+        nbytes = max(tsqr_mixed_workspace_bytes(self.plan), 256)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.dev)
+
+    def run(self, A_flat, R=None):
+        torch = self.torch
+        if A_flat.dtype != torch.float32:
+            raise TypeError("A must be float32")
+        if R is None:
+            R = torch.empty((self.batch, self.n, self.n), dtype=torch.float64, device=self.dev)
+        fb = (ctypes.c_int * max(self.batch, 1))()
+        st = tsqr_mixed_exec(self.plan, A_flat.data_ptr(), R.data_ptr(), self.n, fb, self.ws.data_ptr(),
+                             self.ws.numel(), _stream_ptr(torch, self.dev))
+        _check("tsqr_mixed_exec", st, self.h)
+        return R, [int(fb[i]) for i in range(self.batch)]
+
+    def __del__(self):
+        try:
+            if getattr(self, "plan", None):
+                tsqr_mixed_plan_destroy(self.plan)
                 self.plan = None
         except Exception:
             pass

@@ -217,3 +217,34 @@ def test_batch_plan_empty(ph):
         assert tsqr.lib().tsqr_batch_exec(p, None, None, 50, None, 0, None) == 0
     finally:
         tsqr.tsqr_batch_plan_destroy(p)
+
+
+def test_mixed_plan_checks_and_workspace(ph):
+    L = tsqr.lib()
+    out = ctypes.c_void_p()
+    assert L.tsqr_mixed_plan_create(None, 2, 100, 8, 100, 800, ctypes.byref(out)) == -1
+    assert L.tsqr_mixed_plan_create(ph, -1, 100, 8, 100, 800, ctypes.byref(out)) == -2
+    assert L.tsqr_mixed_plan_create(ph, 2, -1, 8, 100, 800, ctypes.byref(out)) == -3
+    assert L.tsqr_mixed_plan_create(ph, 2, 100, -1, 100, 800, ctypes.byref(out)) == -4
+    assert L.tsqr_mixed_plan_create(ph, 2, 100, 8, 99, 800, ctypes.byref(out)) == -5
+    assert L.tsqr_mixed_plan_create(ph, 2, 100, 8, 100, 799, ctypes.byref(out)) == -6
+    assert L.tsqr_mixed_plan_create(ph, 2, 100, 8, 100, 800, None) == -7
+    assert L.tsqr_mixed_plan_create(ph, 2, 100, 65, 100, 6500, ctypes.byref(out)) == tsqr.TSQR_ERR_UNSUPPORTED
+    p = tsqr.tsqr_mixed_plan_create(ph, 3, 10000, 50, 10000, 500000)
+    try:
+        need = tsqr.tsqr_mixed_workspace_bytes(p)
+        # FP32 batch workspace + R~ + Gram slots (3 blocks of 4096 rows, 50x50)
+        # + flags + one FP64 instance + its FP64 workspace
+        assert need > 3 * 3 * 50 * 50 * 8 + 10000 * 50 * 8
+        buf = ctypes.create_string_buffer(need + 512)
+        ws = (ctypes.addressof(buf) + 255) // 256 * 256
+        assert L.tsqr_mixed_exec(None, 1, 1, 50, None, ws, need, None) == -1
+        assert L.tsqr_mixed_exec(p, None, 1, 50, None, ws, need, None) == -2
+        assert L.tsqr_mixed_exec(p, 1, None, 50, None, ws, need, None) == -3
+        assert L.tsqr_mixed_exec(p, 1, 1, 49, None, ws, need, None) == -4
+        assert L.tsqr_mixed_exec(p, 1, 1, 50, None, None, need, None) == -6
+        assert L.tsqr_mixed_exec(p, 1, 1, 50, None, ws, need - 1, None) == -7
+        assert L.tsqr_mixed_exec(p, 1, 1, 50, None, ws, need, None) == tsqr.TSQR_ERR_NO_DEVICE
+    finally:
+        tsqr.tsqr_mixed_plan_destroy(p)
+    assert L.tsqr_mixed_workspace_bytes(None) == -1
