@@ -13,6 +13,11 @@ leaf+tree kernel.  Prints ONE JSON line on stdout; progress goes to stderr.
 The warmup is long enough (about 50 ms of kernel time) for the GPU clocks to
 settle before the timed steps.
 
+The ``mixed`` object measures 256 FP32-stored instances of 2^16 x 50 with
+condition numbers 1..1e8: FP32 TSQR followed by one FP64 correction, against
+the plain FP64 batched TSQR of the same data and the FP32 TSQR alone, with
+sampled accuracy against the oracle.
+
 The ``batched`` object of the line measures the ragged batch (4096 instances,
 m log-uniform in [64, 65536], n = 50, FP32) three ways: one batched launch per
 step, a Python loop of single-matrix calls, and the same loop captured once
@@ -182,6 +187,88 @@ def time_batched(torch, tsqr, inputs, steps, warmup, n=50, count=4096):
     return out
 
 
+def time_mixed(torch, tsqr, inputs, steps, warmup, batch=256, m=1 << 16, n=50):
+    """Conditioned batch stored in FP32: FP32 TSQR + FP64 correction vs the
+    plain FP64 batched TSQR (on an FP64 copy) and the FP32 TSQR alone."""
+    import concurrent.futures as cf
+    import numpy as np
+    t = time.perf_counter()
+    kappas = 10.0 ** (8.0 * np.arange(batch) / (batch - 1))
+    flat = np.empty(batch * m * n, dtype=np.float32)
+
+    def gen(i):
+        flat[i * m * n:(i + 1) * m * n] = inputs.conditioned(m, n, float(kappas[i]), seed=[3, i]).T.ravel()
+
+    with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as pool:
+        list(pool.map(gen, range(batch)))
+    log(f"mixed: {batch} instances m={m} n={n} fp32 storage, kappa 1..1e8 (generated in {time.perf_counter() - t:.1f} s)")
+    Ad = torch.from_numpy(flat).cuda()
+    mp = tsqr.MixedPlan(batch, m, n)
+
+    def timed(fn, k, w):
+        for _ in range(w):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    k = max(1, min(steps, 10))
+    R = torch.empty((batch, n, n), dtype=torch.float64, device="cuda")
+    fb = [0]
+
+    def run_mixed():
+        fb[0] = mp.run(Ad, R)[1]
+
+    ms_mixed = timed(run_mixed, k, min(warmup, 3))
+    Rm = R.cpu().numpy()
+    fallbacks = int(sum(fb[0]))
+    sizes = np.full(batch, m, dtype=np.int64)
+    offsets = np.arange(batch, dtype=np.int64) * m * n
+    p32 = tsqr.BatchPlan(sizes, offsets, n, torch.float32)
+    R32 = torch.empty((batch, n, n), dtype=torch.float32, device="cuda")
+    ms_32 = timed(lambda: p32.run(Ad, R32), k, min(warmup, 3))
+    A64 = Ad.double()
+    p64 = tsqr.BatchPlan(sizes, offsets, n, torch.float64)
+    R64 = torch.empty((batch, n, n), dtype=torch.float64, device="cuda")
+    ms_64 = timed(lambda: p64.run(A64, R64), k, min(warmup, 3))
+    R32 = R32.cpu().numpy()
+    del A64, p64, R64, Ad
+    torch.cuda.empty_cache()
+    flops = 2.0 * batch * m * n * n
+    log(f"mixed: {ms_mixed:.2f} ms ({fallbacks} fallbacks); fp64 plain {ms_64:.2f} ms; fp32 alone {ms_32:.2f} ms")
+    return {
+        "workload": f"{batch} instances m={m} n={n}, A = U diag(kappa^(-j/49)) V^T stored in fp32, "
+                    "kappa_i = 10^(8 i/255), seeds (3, i)",
+        "value": batch / (ms_mixed * 1e-3), "unit": "instances/s", "ms_per_step": ms_mixed, "steps": k,
+        "fallbacks_to_fp64": fallbacks,
+        "plain_fp64_batched": {"value": batch / (ms_64 * 1e-3), "ms_per_step": ms_64,
+                               "note": "on an fp64 copy of the same data (conversion untimed)"},
+        "fp32_tsqr_alone": {"value": batch / (ms_32 * 1e-3), "ms_per_step": ms_32},
+        "speedup_vs_plain_fp64": ms_64 / ms_mixed,
+        "achieved_TFLOPs_2mn2": flops / (ms_mixed * 1e-3) / 1e12,
+    }, (flat, kappas, Rm, R32)
+
+
+def mixed_accuracy(oracle, np, data, m=1 << 16, n=50, picks=(0, 64, 128, 160, 192, 224, 255)):
+    """relF against the oracle (FP64 on the stored FP32 values) for sampled
+    instances across the kappa range, for the mixed result and FP32 alone."""
+    flat, kappas, Rm, R32 = data
+    out = []
+    for i in picks:
+        A = np.asfortranarray(flat[i * m * n:(i + 1) * m * n].reshape(n, m).T.astype(np.float64))
+        Ro = oracle.r_factor(A)
+        nr = np.linalg.norm(Ro)
+        out.append({"kappa": float(kappas[i]), "relF_mixed": float(np.linalg.norm(Rm[i].T - Ro) / nr),
+                    "relF_fp32_alone": float(np.linalg.norm(R32[i].T.astype(np.float64) - Ro) / nr)})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +276,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--m", type=int, default=1 << 22)
     ap.add_argument("--n", type=int, default=50)
     ap.add_argument("--profile-copy-bytes", type=int, default=0,
@@ -234,6 +322,7 @@ def main():
     del Ad32
 
     batched = None if args.no_batched else time_batched(torch, tsqr, inputs, args.steps, args.warmup)
+    mixed, mixed_data = (None, None) if args.no_mixed else time_mixed(torch, tsqr, inputs, args.steps, args.warmup)
 
     cpu = None
     acc64 = acc32 = None
@@ -250,6 +339,10 @@ def main():
         Ro32 = oracle.r_factor(A32.astype(np.float64))
         acc32 = float(np.linalg.norm(R32 - Ro32) / np.linalg.norm(Ro32))
         log(f"accuracy vs oracle: fp64 {acc64:.2e}, fp32 {acc32:.2e}")
+        if mixed is not None:
+            mixed["accuracy_vs_oracle"] = mixed_accuracy(oracle, np, mixed_data)
+            log("mixed accuracy: " + ", ".join(f"k={a['kappa']:.0e}: {a['relF_mixed']:.1e} (fp32 {a['relF_fp32_alone']:.1e})"
+                                                 for a in mixed["accuracy_vs_oracle"]))
 
     if args.profile_copy_bytes > 0:
         src = torch.empty(args.profile_copy_bytes, dtype=torch.uint8, device="cuda")
@@ -285,6 +378,7 @@ def main():
                  "kernel_ms": ms_kernel32, "achieved_TFLOPs": tflops32, "peak": PEAK_FP32_TFLOPS,
                  "frac": tflops32 / PEAK_FP32_TFLOPS},
         "batched": batched,
+        "mixed": mixed,
         "wall_s_timed": wall,
     }
     print(json.dumps(out), flush=True)

@@ -527,7 +527,8 @@ struct tsqr_mixed_plan_s {
     tsqr_batch_plan_t inner;     // the FP32 batched factorization
     int64_t rows_per_block;
     int blocks;
-    int64_t off_inner, inner_bytes, off_rt, off_part, off_flags, off_a64, off_ws64, ws64_bytes, ws_bytes;
+    int64_t off_inner, inner_bytes, off_rt, off_rp, rp_stride, off_part, off_flags, off_a64, off_ws64, ws64_bytes,
+        ws_bytes;
 };
 
 namespace {
@@ -599,6 +600,9 @@ int tsqr_mixed_plan_create(tsqr_handle_t h, int64_t batch, int64_t m, int64_t n,
     off += align_up(p->inner_bytes > 0 ? p->inner_bytes : 0, kAlign);
     p->off_rt = off;
     off += align_up(batch * n * n * 4, kAlign);
+    p->off_rp = off;
+    p->rp_stride = (int64_t)nc * (nc + 1) / 2 + nc;
+    off += align_up(batch * p->rp_stride * 8, kAlign);
     p->off_part = off;
     off += align_up(batch * p->blocks * W * W * 8, kAlign);
     p->off_flags = off;
@@ -654,6 +658,8 @@ int tsqr_mixed_exec(tsqr_mixed_plan_t plan, const float* A, double* R, int64_t l
     a.stride_a = plan->stride_a;
     a.n = (int)plan->n;
     a.Rt = Rt;
+    a.Rp = reinterpret_cast<double*>(base + plan->off_rp);
+    a.rp_stride = (int)plan->rp_stride;
     a.part = reinterpret_cast<double*>(base + plan->off_part);
     a.rows_per_block = plan->rows_per_block;
     a.blocks = plan->blocks;

@@ -91,6 +91,8 @@ struct MixedArgs {
     int64_t stride_a;
     int n;
     const float* Rt;       // R~ of instance b at Rt + b * n * n, column-major, ld n
+    double* Rp;            // per instance: R~ in FP64 packed by columns, then 1/diag (NC values)
+    int rp_stride;         // elements per instance in Rp
     double* part;          // per (instance, row block): W x W partial Gram sums
     int64_t rows_per_block;
     int blocks;            // row blocks per instance

@@ -42,27 +42,41 @@ __device__ __forceinline__ void gram_block(int t, int& I, int& J)
     J = I + left;
 }
 
+// R~ of every instance in FP64, packed by rows ((i, j) at off(i) + j - i, as
+// for the leaf triangles), extended by the identity past column n (padding
+// columns then solve to 0), followed by the reciprocals of its diagonal.
+template <int NC>
+__global__ void __launch_bounds__(kWave) mixed_prep_kernel(MixedArgs a)
+{
+    constexpr int NT = Tri<NC>::kSize;
+    const int lane = threadIdx.x;
+    const int b = blockIdx.x;
+    const int n = a.n;
+    const float* Rt = a.Rt + (int64_t)b * n * n;
+    double* out = a.Rp + (int64_t)b * a.rp_stride;
+    for (int idx = lane; idx < NT; idx += kWave) {
+        int i = 0;
+        while (Tri<NC>::off(i + 1) <= idx) ++i;
+        const int j = i + (idx - Tri<NC>::off(i));
+        out[idx] = (j < n) ? (double)Rt[i + j * n] : (i == j ? 1.0 : 0.0);
+    }
+    for (int j = lane; j < NC; j += kWave) out[NT + j] = (j < n) ? 1.0 / (double)Rt[j + j * n] : 1.0;
+}
+
 template <int NC>
 __global__ void __launch_bounds__(kWave) mixed_gram_kernel(MixedArgs a)
 {
     constexpr int S = GramTile<NC>::S;
     constexpr int W = GramTile<NC>::W;
     constexpr int YS = W + 1;                              // LDS row stride of Y
-    __shared__ double Rl[NC * (NC + 1) / 2];               // R~ packed by columns
-    __shared__ double invd[NC];
+    constexpr int NT = Tri<NC>::kSize;
     __shared__ double Y[kWave * YS];
     const int lane = threadIdx.x;
     const int b = blockIdx.y;
     const int n = a.n;
-    const float* Rt = a.Rt + (int64_t)b * n * n;
-    // R~ with an identity extension past column n (padding columns solve to 0)
-    for (int idx = lane; idx < NC * (NC + 1) / 2; idx += kWave) {
-        int j = 0;
-        while ((j + 1) * (j + 2) / 2 <= idx) ++j;
-        const int i = idx - j * (j + 1) / 2;
-        Rl[idx] = (j < n) ? (double)Rt[i + j * n] : (i == j ? 1.0 : 0.0);
-    }
-    for (int j = lane; j < NC; j += kWave) invd[j] = (j < n) ? 1.0 / (double)Rt[j + j * n] : 1.0;
+    // R~ is the same for every lane: read through the scalar unit, so each
+    // forward-substitution FMA takes its R~ operand from a scalar register
+    const double* __restrict__ Rp = a.Rp + (int64_t)b * a.rp_stride;
     for (int idx = lane; idx < kWave * YS; idx += kWave) Y[idx] = 0.0;
     wave_sync();
 
@@ -77,28 +91,38 @@ __global__ void __launch_bounds__(kWave) mixed_gram_kernel(MixedArgs a)
     const float* A = a.A + (int64_t)b * a.stride_a;
     const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_block;
     const int64_t r1 = (r0 + a.rows_per_block < a.m) ? r0 + a.rows_per_block : a.m;
-    for (int64_t base = r0; base < r1; base += kWave) {
+    // this lane's row of the next 64-row block, loaded one block ahead
+    float nxt[NC];
+    auto load_rows = [&](int64_t base) {
         const int64_t row = base + lane;
         const bool ok = row < r1;
-        double y[NC];
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
             const bool in = ok && j < n;
             const float v = A[in ? row + (int64_t)j * a.lda : 0];
-            y[j] = in ? (double)v : 0.0;
+            nxt[j] = in ? v : 0.0f;
         }
-        // forward substitution y := y R~^-1 (y_j needs y_0..y_{j-1})
+    };
+    if (r0 < r1) load_rows(r0);
+    for (int64_t base = r0; base < r1; base += kWave) {
+        double y[NC];
 #pragma unroll
-        for (int j = 0; j < NC; ++j) {
-            double t = y[j];
+        for (int j = 0; j < NC; ++j) y[j] = (double)nxt[j];
+        if (base + kWave < r1) load_rows(base + kWave);
+        // y := y R~^-1, one row of R~ at a time: after step i, y_i is final
+        // and the updates of the step are independent
 #pragma unroll
-            for (int i = 0; i < j; ++i) t = fmadd(-y[i], Rl[j * (j + 1) / 2 + i], t);
-            y[j] = t * invd[j];
+        for (int i = 0; i < NC; ++i) {
+            const double yi = y[i] * Rp[NT + i];
+            y[i] = yi;
+#pragma unroll
+            for (int j = i + 1; j < NC; ++j) y[j] = fmadd(-yi, Rp[Tri<NC>::off(i) + j - i], y[j]);
         }
 #pragma unroll
         for (int j = 0; j < NC; ++j) Y[lane * YS + j] = y[j];
         wave_sync();
         if (lane < GramTile<NC>::kBlocks) {
+#pragma unroll 8
             for (int r = 0; r < kWave; ++r) {
                 double yi[S], yj[S];
 #pragma unroll
