@@ -12,7 +12,10 @@
 //   * Leaves then combine with the paper's operator qr(R1, R2) over a binary
 //     tree pairing leaf i with i + 2^level (lower index on top), the merge done
 //     by whichever wavefront of the pair arrives last (atomic ticket), so no
-//     wavefront ever waits on another.
+//     wavefront ever waits on another.  A merge has only NC rows, so it uses a
+//     second layout: one column of R2 per lane (merge_columns).  Workgroups
+//     are numbered onto leaves so that tree siblings share an XCD and its L2
+//     (xcd_local_leaf).
 //   * The root flips rows with a negative diagonal (section 2's positive
 //     diagonal convention) and writes R.
 //
@@ -23,7 +26,8 @@
 // row.  A dot product over the chunk's rows is then a sum over RPL registers
 // and over only 16 lanes, which goes through LDS in one transpose (each lane
 // adds 16 values); the pivot column reaches all lane rows by one ds_bpermute
-// per register.
+// per register, and each column's update coefficient reaches its lane row by
+// a DPP row broadcast.
 //
 // Per Householder step j (x = C(:,j), k > j the trailing columns):
 //     sigma^2 = x.x,  d_k = x.C(:,k)
@@ -379,7 +383,7 @@ __device__ __forceinline__ void merge_chunk(T (&c)[RPL][Slots<NC>::NS], T* Rs, T
 //
 // R := qr([R1; R2]) for two NC x NC upper triangles, the operator of section 2
 // in the structured form of Table 3 (only rows 0..J of R2 take part in step J).
-// R1 is packed by rows in LDS (Rs, with one spare cell after it); lane k holds
+// R1 is packed by rows in LDS (Rs, padded past the triangle); lane k holds
 // column k of R2 in registers (v[i] = R2(i, k), zero below the diagonal).  In
 // step J every lane fetches the pivot column R2(0:J, J) from lane J's
 // registers (ds_bpermute) and forms its own dot product with it locally

@@ -198,3 +198,18 @@ def test_full_ragged_batch_fp32_sampled():
     for b in range(4096):
         Rg = r_of(Rb, b, n)
         assert np.all(np.tril(Rg, -1) == 0) and np.all(np.diag(Rg) > 0), b
+
+
+def test_full_ragged_batch_fp64_sampled():
+    """The same ragged batch in FP64 (7.9 GB of FP32 data promoted: 15.7 GB)."""
+    n = 50
+    flat, sizes, offsets = inputs.batched_uniform(4096, n, 64, 65536, seed=2, dtype=np.float32)
+    Ad = torch.from_numpy(flat).cuda().double()
+    plan = tsqr.BatchPlan(sizes, offsets, n, torch.float64)
+    Rb = plan.run(Ad).cpu().numpy()
+    del Ad
+    rng = np.random.default_rng(1)
+    picks = set(rng.choice(4096, 12, replace=False).tolist()) | {int(np.argmax(sizes))}
+    for b in sorted(picks):
+        A = np.asfortranarray(inputs.instance(flat, sizes, offsets, b, n).astype(np.float64))
+        assert relF(r_of(Rb, b, n), oracle.r_factor(A)) < TOL64, b

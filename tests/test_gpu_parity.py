@@ -267,3 +267,47 @@ def test_full_size_fp32_uniform_vs_oracle():
     R = gpu_r(A32)
     Ro = oracle.r_factor(A32.astype(np.float64))
     assert relF(R.astype(np.float64), Ro) < TOL32
+
+
+def test_plain_call_in_hip_graph_matches_eager():
+    """One call is two kernel launches and no memset, so it can be captured;
+    every replay (with eager work between them) equals the eager result."""
+    A = inputs.uniform(70000, 50, 21)
+    Ad = to_dev(A)
+    h = tsqr.handle(0)
+    ws = tsqr.workspace(70000, 50, torch.float64)
+    eager = tsqr.geqr_r(Ad, ws=ws, h=h).clone()
+    R = torch.empty((50, 50), dtype=torch.float64, device="cuda").t()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        tsqr.geqr_r(Ad, R=R, ws=ws, h=h)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        tsqr.geqr_r(Ad, R=R, ws=ws, h=h)
+    for i in range(4):
+        R.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(R, eager), i
+        tsqr.geqr_r(Ad, ws=ws, h=h)
+        torch.cuda.synchronize()
+
+
+def test_mixed_and_batch_argument_errors_with_device():
+    h = tsqr.handle(0)
+    L = tsqr.lib()
+    p = tsqr.tsqr_mixed_plan_create(h, 2, 100, 8, 100, 800)
+    try:
+        need = tsqr.tsqr_mixed_workspace_bytes(p)
+        ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+        assert L.tsqr_mixed_exec(p, None, 1, 8, None, ws.data_ptr(), need, None) == -2
+        assert L.tsqr_mixed_exec(p, 1, 1, 8, None, ws.data_ptr() + 8, need, None) == -6
+        assert L.tsqr_mixed_exec(p, 1, 1, 8, None, ws.data_ptr(), need - 1, None) == -7
+    finally:
+        tsqr.tsqr_mixed_plan_destroy(p)
+    with pytest.raises(tsqr.TsqrError):
+        tsqr.MixedPlan(1, 100, 65)
