@@ -39,6 +39,7 @@ def instances():
     text = open(os.path.join(CSRC, "tsqr_instances.h")).read()
     leaf_block = re.search(r"#define TSQR_LEAF_INSTANCES\(X\)(.*?)\n\n", text, re.S).group(1)
     op_block = re.search(r"#define TSQR_OP_INSTANCES\(O\)(.*?)\n\n", text, re.S).group(1)
+    qr_block = re.search(r"#define TSQR_QR_INSTANCES\(Q\)(.*?)\n\n", text, re.S).group(1)
     units = [("common", ["-DTSQR_INST_COMMON"])]
     for tag, nc, rpl in re.findall(r"X\((\w+),\s*(\d+),\s*(\d+)\)", leaf_block):
         units.append((f"leaf_{tag}_{nc}_{rpl}",
@@ -46,10 +47,14 @@ def instances():
                        f"-DTSQR_INST_RPL={rpl}"]))
     for tag, nc in re.findall(r"O\((\w+),\s*(\d+)\)", op_block):
         units.append((f"op_{tag}_{nc}", ["-DTSQR_INST_OP", f"-DTSQR_INST_TAG={tag}", f"-DTSQR_INST_NC={nc}"]))
+    for tag, nc, rpl in re.findall(r"Q\((\w+),\s*(\d+),\s*(\d+)\)", qr_block):
+        units.append((f"qr_{tag}_{nc}_{rpl}",
+                      ["-DTSQR_INST_QR", f"-DTSQR_INST_TAG={tag}", f"-DTSQR_INST_NC={nc}",
+                       f"-DTSQR_INST_RPL={rpl}"]))
     return units
 
 
-KERNEL_DEPS = ["tsqr_inst.hip", "tsqr_device.h", "tsqr_mixed.h", "tsqr_internal.h", "tsqr_instances.h"]
+KERNEL_DEPS = ["tsqr_inst.hip", "tsqr_device.h", "tsqr_mixed.h", "tsqr_q.h", "tsqr_internal.h", "tsqr_instances.h"]
 API_DEPS = ["tsqr_api.cpp", "tsqr_internal.h", "tsqr_instances.h", "tsqr_mixed.h", "tsqr_device.h"]
 
 
@@ -92,7 +97,7 @@ def build(force: bool = True, jobs: int | None = None, verbose: bool = False) ->
     objs.append(api_obj)
     jobs = jobs or min(16, os.cpu_count() or 4)
     # the largest units first so the pool finishes evenly
-    tasks.sort(key=lambda t: (0 if "leaf_" in t[0] else 1, t[0]))
+    tasks.sort(key=lambda t: (0 if ("leaf_" in t[0] or "qr_" in t[0]) else 1, t[0]))
     with cf.ThreadPoolExecutor(max_workers=jobs) as pool:
         for done in pool.map(_compile, tasks):
             os.replace(done + ".tmp", done)

@@ -275,12 +275,25 @@ __device__ __forceinline__ void prefetch_slot(T (&c)[RPL][NS], int slot, Prefetc
     pf.cols_left -= 4;
 }
 
+// Where a leaf in the Q-factor mode writes the reflectors of its current
+// chunk: column J of V gets the chunk part s*x of reflector J, tau[J] its tau.
+// V has a row for every row of every chunk, so the rows of a partial last
+// chunk past the end of A (whose entries are zero) are stored like the others.
+template <typename T>
+struct VSink {
+    T* V;
+    int64_t ldv;
+    T* tau;
+    int64_t cbase;    // first row of the chunk
+    int n;
+};
+
 // Step J of R := qr([R; C]) with R packed in LDS (Rs) and C in registers.  The
 // NC steps of a chunk are unrolled at compile time so every register index is
 // static and the scheduler can overlap consecutive steps.
-template <typename T, int NC, int RPL, int J>
+template <typename T, int NC, int RPL, int J, bool WQ>
 __device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* red, int q, int p,
-                                        int kcol, int spare, Prefetch<T, RPL>& pf)
+                                        int kcol, int spare, Prefetch<T, RPL>& pf, const VSink<T>& vs)
 {
     constexpr int NS = Slots<NC>::NS;
     constexpr int QJ = J % 4, SJ = J / 4;     // lane row and slot holding column J
@@ -334,6 +347,14 @@ __device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* re
     for (int r = 1; r < RPL; ++r) sp = fmadd(x[r], x[r], sp);
     const T sigma2 = row_allreduce16(sp);
     const Reflector<T> h = make_reflector(alpha, sigma2);
+    if constexpr (WQ) {
+        if (q == 0 && J < vs.n) {
+            T* col = vs.V + vs.cbase + p + (int64_t)J * vs.ldv;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) col[16 * r] = h.s * x[r];
+        }
+        if (q == 0 && p == 0) vs.tau[J] = h.tau;
+    }
 
     if constexpr (K > 0) {
 #pragma unroll
@@ -364,9 +385,9 @@ __device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* re
     if constexpr (QJ == 3 || J == NC - 1) prefetch_slot<T, RPL, NS>(c, SJ, pf, p);
 }
 
-template <typename T, int NC, int RPL>
+template <typename T, int NC, int RPL, bool WQ>
 __device__ __forceinline__ void merge_chunk(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* red, int q, int p,
-                                            Prefetch<T, RPL>& pf)
+                                            Prefetch<T, RPL>& pf, const VSink<T>& vs)
 {
     // the column a lane completes in the reduction, passed through an opaque
     // copy so the compiler does not precompute (and keep live) one
@@ -375,7 +396,7 @@ __device__ __forceinline__ void merge_chunk(T (&c)[RPL][Slots<NC>::NS], T* Rs, T
     asm volatile("" : "+v"(kcol));
     const int spare = Tri<NC>::kSize;      // one LDS cell past the triangle
     static_for<0, NC>([&](auto jc) {
-        hh_step<T, NC, RPL, decltype(jc)::value>(c, Rs, red, q, p, kcol, spare, pf);
+        hh_step<T, NC, RPL, decltype(jc)::value, WQ>(c, Rs, red, q, p, kcol, spare, pf, vs);
     });
 }
 
@@ -478,8 +499,11 @@ __device__ __forceinline__ void triangle_to_lds(const T* __restrict__ src, T* ds
 // One leaf of one instance, then that instance's reduction tree: the body
 // shared by the single-matrix kernel and the batched kernel.  `a` describes the
 // instance (its matrix, leaf size and count, triangle slots, tree counters and
-// output); `leaf` is this workgroup's leaf.
-template <typename T, int NC, int RPL>
+// output); `leaf` is this workgroup's leaf.  With WQ (the Q-factor mode) the
+// leaf also writes its reflectors (a.qs.V, a.qs.tau_leaf), every merge those
+// of the operator (a.qs.Vn, a.qs.tau_node), and the root the sign pattern of
+// R's diagonal as the starting block of Q (a.qs.qblk, slot 0).
+template <typename T, int NC, int RPL, bool WQ = false>
 __device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T>& a, int leaf, T* Rs, T* red)
 {
     constexpr int CH = 16 * RPL;                  // rows per chunk
@@ -511,7 +535,15 @@ __device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T>& a, int lea
         const int64_t nchunks = (r1 - r0 + CH - 1) / CH;
         for (int64_t t = 0; t < nchunks; ++t) {
             Prefetch<T, RPL> pf = make_prefetch<T, RPL>(a.A, a.lda, a.n, r0 + (t + 1) * CH, r1, q, p);
-            merge_chunk<T, NC, RPL>(c, Rs, red, q, p, pf);
+            VSink<T> vs{};
+            if constexpr (WQ) {
+                vs.V = a.qs.V;
+                vs.ldv = a.qs.ldv;
+                vs.cbase = r0 + t * CH;
+                vs.n = a.n;
+                vs.tau = a.qs.tau_leaf + (vs.cbase / CH) * NC;
+            }
+            merge_chunk<T, NC, RPL, WQ>(c, Rs, red, q, p, pf, vs);
         }
     }
     wave_sync();
@@ -557,7 +589,19 @@ __device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T>& a, int lea
             triangle_to_lds<T, NC>(a.tri + (int64_t)partner * NT, Rs);
         }
         wave_sync();
-        merge_columns<T, NC, Mode::Merge>(v, Rs, nullptr);
+        if constexpr (WQ) {
+            // the operator's reflectors: V (the R2 parts, column `lane` in v)
+            // and tau (written to LDS by the merge)
+            merge_columns<T, NC, Mode::Operator>(v, Rs, red);
+            wave_sync();
+            T* vn = a.qs.Vn + (int64_t)id * NT;
+#pragma unroll
+            for (int i = 0; i < NC; ++i)
+                if (i <= lane && lane < NC) vn[Tri<NC>::off(i) + lane - i] = v[i];
+            if (lane < NC) a.qs.tau_node[(int64_t)id * NC + lane] = red[lane];
+        } else {
+            merge_columns<T, NC, Mode::Merge>(v, Rs, nullptr);
+        }
         wave_sync();
         node = left;
         ++level;
@@ -579,6 +623,16 @@ __device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T>& a, int lea
         }
         a.R[i + (int64_t)k * a.ldr] = v;
     }
+    if constexpr (WQ) {
+        // R = D R_raw with D the diagonal of signs, so Q = Q_raw D: the tree
+        // pass starts from [D; 0] (identity past column n)
+        for (int idx = lane; idx < NC * NC; idx += kWave) {
+            const int i = idx % NC, k = idx / NC;
+            T d = T(0);
+            if (i == k) d = (k < n && __builtin_signbit(Rs[Tri<NC>::off(k)])) ? T(-1) : T(1);
+            a.qs.qblk[idx] = d;
+        }
+    }
 }
 
 // Workgroups are dispatched to the 8 XCDs in turn (workgroup g to XCD g mod 8),
@@ -594,12 +648,12 @@ __device__ __forceinline__ int xcd_local_leaf(int g, int P)
     return x * a + (x < b ? x : b) + g / kXcds;
 }
 
-template <typename T, int NC, int RPL>
+template <typename T, int NC, int RPL, bool WQ = false>
 __global__ void __launch_bounds__(kWave) tsqr_leaf_tree_kernel(LeafTreeArgs<T> a)
 {
     __shared__ T Rs[Tri<NC>::kPadded];
     __shared__ T red[LdsScratch<NC>::kElems];
-    leaf_tree_body<T, NC, RPL>(a, xcd_local_leaf(blockIdx.x, a.leaves), Rs, red);
+    leaf_tree_body<T, NC, RPL, WQ>(a, xcd_local_leaf(blockIdx.x, a.leaves), Rs, red);
 }
 
 // Many independent instances in one launch: workgroup g takes tile
@@ -625,6 +679,7 @@ __global__ void __launch_bounds__(kWave) tsqr_batch_kernel(BatchArgs<T> b)
     a.tickets = b.tickets + in.ticket_off;
     a.R = b.R + (int64_t)t.inst * b.ldr * b.n;
     a.ldr = b.ldr;
+    a.qs = QStore<T>{};
     leaf_tree_body<T, NC, RPL>(a, t.leaf, Rs, red);
 }
 

@@ -1,10 +1,13 @@
 // tsqr_inst.hip -- one kernel instantiation of libtsqr.so, selected at compile
 // time: -DTSQR_INST_LEAF -DTSQR_INST_TAG=f64|f32 -DTSQR_INST_NC=<n> -DTSQR_INST_RPL=<r>
-// for a leaf+tree kernel, -DTSQR_INST_OP with TAG and NC for an operator
-// kernel, or -DTSQR_INST_COMMON for the small helper kernels.
+// for a leaf+tree kernel, -DTSQR_INST_QR with TAG, NC and RPL for the
+// Q-factor kernels, -DTSQR_INST_OP with TAG and NC for an operator (and, in
+// f64, the mixed-precision) kernels, or -DTSQR_INST_COMMON for the small
+// helper kernels.
 #include "tsqr_device.h"
 #include "tsqr_internal.h"
 #include "tsqr_mixed.h"
+#include "tsqr_q.h"
 
 
 namespace tsqr {
@@ -43,6 +46,32 @@ hipError_t TSQR_BATCH_FN2(TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL)(const Batc
     if (tiles <= 0) return hipSuccess;
     hipLaunchKernelGGL((dev::tsqr_batch_kernel<TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL>), dim3(tiles),
                        dim3(dev::kWave), 0, s, a);
+    return hipGetLastError();
+}
+#elif defined(TSQR_INST_QR)
+#define TSQR_QR_FN(kind, tag, nc, rpl) launch_##kind##_##tag##_##nc##_##rpl
+#define TSQR_QR_FN2(kind, tag, nc, rpl) TSQR_QR_FN(kind, tag, nc, rpl)
+hipError_t TSQR_QR_FN2(qr_leaf_tree, TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL)(
+    const LeafTreeArgs<TSQR_INST_TAG>& a, hipStream_t s)
+{
+    hipLaunchKernelGGL((dev::tsqr_leaf_tree_kernel<TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL, true>),
+                       dim3(a.leaves), dim3(dev::kWave), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t TSQR_QR_FN2(q_tree, TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL)(const LeafTreeArgs<TSQR_INST_TAG>& a,
+                                                                        int level, int nodes, hipStream_t s)
+{
+    if (nodes <= 0) return hipSuccess;
+    hipLaunchKernelGGL((dev::q_tree_kernel<TSQR_INST_TAG, TSQR_INST_NC>), dim3(nodes), dim3(dev::kWave), 0, s, a,
+                       level);
+    return hipGetLastError();
+}
+hipError_t TSQR_QR_FN2(q_leaf, TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL)(const LeafTreeArgs<TSQR_INST_TAG>& a,
+                                                                        TSQR_INST_TAG* Q, int64_t ldq,
+                                                                        hipStream_t s)
+{
+    hipLaunchKernelGGL((dev::q_leaf_kernel<TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL>), dim3(a.leaves),
+                       dim3(dev::kWave), 0, s, a, Q, ldq);
     return hipGetLastError();
 }
 #elif defined(TSQR_INST_OP)
@@ -115,7 +144,7 @@ hipError_t launch_zero_u32(unsigned* p, int64_t count, hipStream_t s)
     return hipGetLastError();
 }
 #else
-#error "select an instantiation with -DTSQR_INST_LEAF, -DTSQR_INST_OP or -DTSQR_INST_COMMON"
+#error "select an instantiation with -DTSQR_INST_LEAF, -DTSQR_INST_QR, -DTSQR_INST_OP or -DTSQR_INST_COMMON"
 #endif
 
 }  // namespace tsqr

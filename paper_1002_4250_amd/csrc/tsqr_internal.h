@@ -9,6 +9,18 @@
 
 namespace tsqr {
 
+// Reflector storage of the Q-factor mode (unused by the R-only kernels).
+template <typename T>
+struct QStore {
+    T* V;                 // (chunks x chunk rows) x n, leading dimension ldv: the chunk part s*x of
+                          // every leaf reflector, zero in the rows of a last chunk past the end of A
+    int64_t ldv;
+    T* tau_leaf;          // (global chunk index) x NC
+    T* Vn;                // per tree node (counter id): packed NC x NC triangle, the R2 part of its reflectors
+    T* tau_node;          // per tree node: NC
+    T* qblk;              // per leaf: NC x NC column-major block of Q (output of the tree pass)
+};
+
 template <typename T>
 struct LeafTreeArgs {
     const T* A;           // m-by-n, column-major
@@ -21,6 +33,7 @@ struct LeafTreeArgs {
     unsigned* tickets;    // workspace: P tree counters, zero on entry and on exit
     T* R;                 // n-by-n output
     int64_t ldr;
+    QStore<T> qs;         // Q-factor mode only
 };
 
 // Batched execution: per-instance description and the (instance, leaf) tiles.
@@ -72,6 +85,17 @@ TSQR_OP_INSTANCES(TSQR_DECLARE_OP)
 #undef TSQR_DECLARE_OP
 
 hipError_t launch_zero_u32(unsigned* p, int64_t count, hipStream_t s);
+
+// Q-factor mode (FP64): the leaf+tree kernel storing its reflectors, one
+// launch per tree level top-down, then one pass over the leaves.
+#define TSQR_QR_INSTANCES_DECL(tag, NC, RPL)                                                          \
+    hipError_t launch_qr_leaf_tree_##tag##_##NC##_##RPL(const LeafTreeArgs<tag>& a, hipStream_t s);  \
+    hipError_t launch_q_tree_##tag##_##NC##_##RPL(const LeafTreeArgs<tag>& a, int level, int nodes,   \
+                                                   hipStream_t s);                                    \
+    hipError_t launch_q_leaf_##tag##_##NC##_##RPL(const LeafTreeArgs<tag>& a, tag* Q, int64_t ldq,    \
+                                                   hipStream_t s);
+TSQR_QR_INSTANCES(TSQR_QR_INSTANCES_DECL)
+#undef TSQR_QR_INSTANCES_DECL
 hipError_t launch_convert_f32_f64(const float* A, int64_t m, int64_t n, int64_t lda, double* out, hipStream_t s);
 
 // Register blocking of G: a 10 x 10 grid of S x S blocks covers the padded

@@ -48,6 +48,8 @@ SIGNATURES = [
     ("tsqr_batch_workspace_bytes", _i64, [_p]),
     ("tsqr_batch_plan_info", _i, [_p, _pi64, _pi64, _pi64]),
     ("tsqr_batch_exec", _i, [_p, _p, _p, _i64, _p, _i64, _p]),
+    ("tsqr_qr_workspace_bytes", _i64, [_p, _i64, _i64]),
+    ("tsqr_geqr_qr_f64", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
     ("tsqr_mixed_plan_create", _i, [_p, _i64, _i64, _i64, _i64, _i64, ctypes.POINTER(_p)]),
     ("tsqr_mixed_plan_destroy", _i, [_p]),
     ("tsqr_mixed_workspace_bytes", _i64, [_p]),
@@ -373,3 +375,40 @@ class MixedPlan:
                 self.plan = None
         except Exception:
             pass
+
+
+# ---- the Q factor -----------------------------------------------------------------
+
+def tsqr_qr_workspace_bytes(handle, m, n) -> int:
+    v = lib().tsqr_qr_workspace_bytes(handle, int(m), int(n))
+    if v < 0:
+        raise TsqrError("tsqr_qr_workspace_bytes", int(v) if v > -1000 else int(-1000 - v))
+    return int(v)
+
+
+def tsqr_geqr_qr_f64(handle, m, n, A, lda, Q, ldq, R, ldr, ws, ws_bytes, stream) -> int:
+    return lib().tsqr_geqr_qr_f64(handle, m, n, A, lda, Q, ldq, R, ldr, ws, ws_bytes, stream)
+
+
+def geqr_qr(A, Q=None, R=None, ws=None, h=None):
+    """A = Q R for a column-major float64 device matrix A (m >= n): Q m x n
+    with orthonormal columns, R n x n upper triangular with diag >= 0, both
+    column-major.  Returns (Q, R)."""
+    import torch
+    if A.dtype != torch.float64:
+        raise TypeError("A must be float64")
+    m, n, lda = _col_major(A)
+    dev = A.device
+    h = h or handle(dev.index or 0)
+    if Q is None:
+        Q = torch.empty((n, m), dtype=A.dtype, device=dev).t()
+    if R is None:
+        R = torch.empty((n, n), dtype=A.dtype, device=dev).t()
+    ldq = Q.stride(1) if n > 1 else max(m, 1)
+    ldr = R.stride(1) if n > 1 else max(n, 1)
+    if ws is None:
+        ws = torch.empty(max(tsqr_qr_workspace_bytes(h, m, n), 256), dtype=torch.uint8, device=dev)
+    st = tsqr_geqr_qr_f64(h, m, n, A.data_ptr(), lda, Q.data_ptr(), ldq, R.data_ptr(), ldr, ws.data_ptr(),
+                          ws.numel(), _stream_ptr(torch, dev))
+    _check("tsqr_geqr_qr_f64", st, h)
+    return Q, R

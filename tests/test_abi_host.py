@@ -248,3 +248,16 @@ def test_mixed_plan_checks_and_workspace(ph):
     finally:
         tsqr.tsqr_mixed_plan_destroy(p)
     assert L.tsqr_mixed_workspace_bytes(None) == -1
+
+
+def test_qr_workspace_query(ph):
+    L = tsqr.lib()
+    assert L.tsqr_qr_workspace_bytes(None, 100, 10) == -1
+    assert L.tsqr_qr_workspace_bytes(ph, -1, 10) == -2
+    assert L.tsqr_qr_workspace_bytes(ph, 10, 11) == -3
+    assert L.tsqr_qr_workspace_bytes(ph, 100, 0) == 0
+    m, n = 100000, 50
+    r_only = tsqr.tsqr_workspace_bytes(ph, m, n, tsqr.TSQR_F64)
+    need = tsqr.tsqr_qr_workspace_bytes(ph, m, n)
+    assert need >= r_only + 8 * m * n
+    assert L.tsqr_geqr_qr_f64(ph, m, n, 1, m, 1, m, 1, n, None, need, None) == -10

@@ -1,0 +1,104 @@
+"""The Q factor formed from the stored TSQR reflectors (tsqr_geqr_qr_f64).
+
+For A of full column rank, Q with R's diagonal positive is unique:
+Q = A R^-1.  The reference is that definition evaluated on the CPU in FP64
+with the oracle's R (a triangular solve).  Checked at 1e-12 relative
+(Frobenius) for the well-conditioned inputs used here, together with the
+defining properties Q^T Q = I and Q R = A (both at 1e-13), and R equal bit for
+bit to the R-only entry point with the same leaf size.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+from paper_1002_4250_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1002_4250_amd import tsqr  # noqa: E402
+
+
+def relF(X, Y):
+    return float(np.linalg.norm(X - Y) / max(np.linalg.norm(Y), 1e-300))
+
+
+def to_dev(A):
+    return torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t()
+
+
+def run_qr(A, leaf_rows=0):
+    h = tsqr.handle(0)
+    tsqr.tsqr_set_option(h, tsqr.TSQR_OPT_LEAF_ROWS, leaf_rows)
+    try:
+        Ad = to_dev(A)
+        Q, R = tsqr.geqr_qr(Ad)
+        Rr = tsqr.geqr_r(Ad)
+        torch.cuda.synchronize()
+        return Q.cpu().numpy(), R.cpu().numpy(), Rr.cpu().numpy()
+    finally:
+        tsqr.tsqr_set_option(h, tsqr.TSQR_OPT_LEAF_ROWS, 0)
+
+
+@pytest.mark.parametrize("m,n,leaf_rows", [(256, 50, 0), (256, 50, 128), (5000, 17, 0), (5000, 17, 256),
+                                           (70000, 50, 0), (70000, 50, 1000), (50, 50, 0), (4097, 64, 384),
+                                           (1000, 1, 0), (9000, 32, 128)])
+def test_q_matches_definition(m, n, leaf_rows):
+    A = inputs.uniform(m, n, 31 + n)
+    Q, R, Rr = run_qr(A, leaf_rows)
+    assert np.array_equal(R, Rr)
+    Ro = oracle.r_factor(A)
+    assert relF(R, Ro) < 1e-10
+    Qdef = scipy.linalg.solve_triangular(Ro, A.T, trans="T", lower=False).T   # A Ro^-1
+    assert relF(Q, Qdef) < 1e-12
+    assert np.linalg.norm(Q.T @ Q - np.eye(n)) / np.sqrt(n) < 1e-13
+    assert relF(Q @ R, A) < 1e-13
+
+
+def test_q_hadamard_exact():
+    """A = Q_true R_true exactly (Q_true = scaled Hadamard columns): Q must
+    reproduce Q_true."""
+    A, Rt = inputs.hadamard_exact(65536, 50, seed=4)
+    Q, R, _ = run_qr(A)
+    assert relF(R, Rt) < 1e-13
+    Qt = scipy.linalg.solve_triangular(Rt, A.T, trans="T", lower=False).T
+    assert relF(Q, Qt) < 1e-13
+
+
+def test_q_full_size_sampled():
+    m, n = 1 << 22, 50
+    A = inputs.uniform(m, n, 1)
+    Ad = to_dev(A)
+    Q, R = tsqr.geqr_qr(Ad)
+    G = (Q.t() @ Q).cpu().numpy()
+    assert np.linalg.norm(G - np.eye(n)) / np.sqrt(n) < 1e-12
+    QR = Q @ R
+    assert float(((QR - Ad).norm() / Ad.norm()).item()) < 1e-13
+    Rn = R.cpu().numpy()
+    rows = np.random.default_rng(0).choice(m, 64, replace=False)
+    Qs = Q.cpu().numpy()[rows]
+    Qdef = scipy.linalg.solve_triangular(Rn, A[rows].T, trans="T", lower=False).T
+    assert relF(Qs, Qdef) < 1e-12
+
+
+def test_q_argument_errors():
+    h = tsqr.handle(0)
+    L = tsqr.lib()
+    assert L.tsqr_geqr_qr_f64(None, 10, 2, 1, 10, 1, 10, 1, 2, 1, 1 << 20, None) == -1
+    assert L.tsqr_geqr_qr_f64(h, -1, 2, 1, 10, 1, 10, 1, 2, 1, 1 << 20, None) == -2
+    assert L.tsqr_geqr_qr_f64(h, 10, 11, 1, 10, 1, 10, 1, 11, 1, 1 << 20, None) == -3
+    assert L.tsqr_geqr_qr_f64(h, 10, 2, None, 10, 1, 10, 1, 2, 1, 1 << 20, None) == -4
+    assert L.tsqr_geqr_qr_f64(h, 10, 2, 1, 9, 1, 10, 1, 2, 1, 1 << 20, None) == -5
+    assert L.tsqr_geqr_qr_f64(h, 10, 2, 1, 10, None, 10, 1, 2, 1, 1 << 20, None) == -6
+    assert L.tsqr_geqr_qr_f64(h, 10, 2, 1, 10, 1, 9, 1, 2, 1, 1 << 20, None) == -7
+    assert L.tsqr_geqr_qr_f64(h, 10, 2, 1, 10, 1, 10, None, 2, 1, 1 << 20, None) == -8
+    assert L.tsqr_geqr_qr_f64(h, 10, 2, 1, 10, 1, 10, 1, 1, 1, 1 << 20, None) == -9
+    need = tsqr.tsqr_qr_workspace_bytes(h, 10, 2)
+    ws = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    assert L.tsqr_geqr_qr_f64(h, 10, 2, 1, 10, 1, 10, 1, 2, None, need, None) == -10
+    assert L.tsqr_geqr_qr_f64(h, 10, 2, 1, 10, 1, 10, 1, 2, ws.data_ptr(), need - 1, None) == -11
+    assert L.tsqr_geqr_qr_f64(h, 10, 0, None, 10, None, 10, None, 1, None, 0, None) == 0
