@@ -9,6 +9,7 @@ which launches a small kernel that clears the tree counters and then the fused
 leaf+tree kernel.  Prints ONE JSON line on stdout; progress goes to stderr.
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 30] [--no-cpu-baseline] [--no-batched]
+        [--no-mixed] [--no-q]
 
 The warmup is long enough (about 50 ms of kernel time) for the GPU clocks to
 settle before the timed steps.
@@ -17,6 +18,9 @@ The ``mixed`` object measures 256 FP32-stored instances of 2^16 x 50 with
 condition numbers 1..1e8: FP32 TSQR followed by one FP64 correction, against
 the plain FP64 batched TSQR of the same data and the FP32 TSQR alone, with
 sampled accuracy against the oracle.
+
+The ``q_factor`` object times A = QR with Q formed explicitly from the stored
+reflectors on the plain instance, with torch.linalg.qr beside it for context.
 
 The ``batched`` object of the line measures the ragged batch (4096 instances,
 m log-uniform in [64, 65536], n = 50, FP32) three ways: one batched launch per
@@ -98,6 +102,53 @@ def time_plain(torch, tsqr, Ad, steps, warmup):
     ms_step = t0.elapsed_time(t1) / steps
     ms_kernel = sum(a.elapsed_time(b) for a, b in ev) / steps
     return ms_step, ms_kernel, wall, R
+
+
+def time_q(torch, tsqr, Ad, steps, warmup):
+    """A = Q R with Q formed explicitly (tsqr_geqr_qr_f64) on the same FP64
+    instance, checked by Q^T Q = I and Q R = A; the library QR of torch
+    (rocSOLVER) on the same matrix is timed beside it for context."""
+    m, n = Ad.shape
+    h = tsqr.handle(0)
+    ws = torch.empty(tsqr.tsqr_qr_workspace_bytes(h, m, n), dtype=torch.uint8, device="cuda")
+    Q = torch.empty((n, m), dtype=Ad.dtype, device="cuda").t()
+    R = torch.empty((n, n), dtype=Ad.dtype, device="cuda").t()
+
+    def timed(fn, k, w):
+        for _ in range(w):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(k):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / k
+
+    k = max(1, min(steps, 20))
+    ms_q = timed(lambda: tsqr.geqr_qr(Ad, Q=Q, R=R, ws=ws, h=h), k, min(warmup, 10))
+    orth = float(torch.linalg.norm(Q.t() @ Q - torch.eye(n, dtype=Ad.dtype, device="cuda")).item()) / n ** 0.5
+    resid = float(((Q @ R - Ad).norm() / Ad.norm()).item())
+    lib_ms = lib_r_ms = None
+    try:
+        lib_ms = timed(lambda: torch.linalg.qr(Ad, mode="reduced"), 3, 1)
+        lib_r_ms = timed(lambda: torch.linalg.qr(Ad, mode="r"), 3, 1)
+    except RuntimeError as e:      # the library path is context only
+        log(f"q: torch.linalg.qr unavailable: {e}")
+    flops = 4.0 * m * n * n        # factorization 2mn^2 + forming Q 2mn^2 (LAPACK's counts for m >> n)
+    gbs_min = 16.0 * m * n / (ms_q * 1e-3) / 1e9
+    log(f"q: {ms_q:.3f} ms per QR with Q ({flops / (ms_q * 1e-3) / 1e12:.2f} TFLOP/s at 4mn^2); "
+        f"orth {orth:.1e} resid {resid:.1e}; torch.linalg.qr {lib_ms} ms (mode r {lib_r_ms} ms)")
+    return {
+        "workload": f"A = QR with explicit Q, m={m} n={n} fp64 (the plain instance)",
+        "value": 1000.0 / ms_q, "unit": "instances/s", "ms_per_step": ms_q, "steps": k,
+        "achieved_TFLOPs_4mn2": flops / (ms_q * 1e-3) / 1e12,
+        "frac_fp64_vector_peak": flops / (ms_q * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+        "min_hbm_GBs_read_A_write_Q": gbs_min,
+        "orthogonality": orth, "residual": resid,
+        "torch_linalg_qr_reduced_ms": lib_ms, "torch_linalg_qr_r_ms": lib_r_ms,
+    }
 
 
 def time_batched(torch, tsqr, inputs, steps, warmup, n=50, count=4096):
@@ -277,6 +328,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-q", action="store_true")
     ap.add_argument("--m", type=int, default=1 << 22)
     ap.add_argument("--n", type=int, default=50)
     ap.add_argument("--profile-copy-bytes", type=int, default=0,
@@ -310,6 +362,7 @@ def main():
     gbs = nbytes / (ms_kernel * 1e-3) / 1e9
     log(f"fp64: {ms_step * 1e3:.1f} us/step, kernel {ms_kernel * 1e3:.1f} us, {tflops:.2f} TFLOP/s, {gbs:.0f} GB/s")
     R64 = R.cpu().numpy()
+    qf = None if args.no_q else time_q(torch, tsqr, Ad, args.steps, args.warmup)
 
     # FP32 variant of the same workload (input = RNE rounding of the FP64 draws)
     A32 = A.astype(np.float32)
@@ -379,6 +432,7 @@ def main():
                  "frac": tflops32 / PEAK_FP32_TFLOPS},
         "batched": batched,
         "mixed": mixed,
+        "q_factor": qf,
         "wall_s_timed": wall,
     }
     print(json.dumps(out), flush=True)
