@@ -9,7 +9,7 @@ which launches a small kernel that clears the tree counters and then the fused
 leaf+tree kernel.  Prints ONE JSON line on stdout; progress goes to stderr.
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 30] [--no-cpu-baseline] [--no-batched]
-        [--no-mixed] [--no-q]
+        [--no-mixed] [--no-q] [--no-library]
 
 The warmup is long enough (about 50 ms of kernel time) for the GPU clocks to
 settle before the timed steps.
@@ -104,7 +104,7 @@ def time_plain(torch, tsqr, Ad, steps, warmup):
     return ms_step, ms_kernel, wall, R
 
 
-def time_q(torch, tsqr, Ad, steps, warmup):
+def time_q(torch, tsqr, Ad, steps, warmup, library=True):
     """A = Q R with Q formed explicitly (tsqr_geqr_qr_f64) on the same FP64
     instance, checked by Q^T Q = I and Q R = A; the library QR of torch
     (rocSOLVER) on the same matrix is timed beside it for context."""
@@ -131,11 +131,12 @@ def time_q(torch, tsqr, Ad, steps, warmup):
     orth = float(torch.linalg.norm(Q.t() @ Q - torch.eye(n, dtype=Ad.dtype, device="cuda")).item()) / n ** 0.5
     resid = float(((Q @ R - Ad).norm() / Ad.norm()).item())
     lib_ms = lib_r_ms = None
-    try:
-        lib_ms = timed(lambda: torch.linalg.qr(Ad, mode="reduced"), 3, 1)
-        lib_r_ms = timed(lambda: torch.linalg.qr(Ad, mode="r"), 3, 1)
-    except RuntimeError as e:      # the library path is context only
-        log(f"q: torch.linalg.qr unavailable: {e}")
+    if library:
+        try:
+            lib_ms = timed(lambda: torch.linalg.qr(Ad, mode="reduced"), 3, 1)
+            lib_r_ms = timed(lambda: torch.linalg.qr(Ad, mode="r"), 3, 1)
+        except RuntimeError as e:      # the library path is context only
+            log(f"q: torch.linalg.qr unavailable: {e}")
     flops = 4.0 * m * n * n        # factorization 2mn^2 + forming Q 2mn^2 (LAPACK's counts for m >> n)
     gbs_min = 16.0 * m * n / (ms_q * 1e-3) / 1e9
     log(f"q: {ms_q:.3f} ms per QR with Q ({flops / (ms_q * 1e-3) / 1e12:.2f} TFLOP/s at 4mn^2); "
@@ -329,6 +330,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-q", action="store_true")
+    ap.add_argument("--no-library", action="store_true", help="skip timing torch.linalg.qr beside the Q factor")
     ap.add_argument("--m", type=int, default=1 << 22)
     ap.add_argument("--n", type=int, default=50)
     ap.add_argument("--profile-copy-bytes", type=int, default=0,
@@ -362,7 +364,7 @@ def main():
     gbs = nbytes / (ms_kernel * 1e-3) / 1e9
     log(f"fp64: {ms_step * 1e3:.1f} us/step, kernel {ms_kernel * 1e3:.1f} us, {tflops:.2f} TFLOP/s, {gbs:.0f} GB/s")
     R64 = R.cpu().numpy()
-    qf = None if args.no_q else time_q(torch, tsqr, Ad, args.steps, args.warmup)
+    qf = None if args.no_q else time_q(torch, tsqr, Ad, args.steps, args.warmup, library=not args.no_library)
 
     # FP32 variant of the same workload (input = RNE rounding of the FP64 draws)
     A32 = A.astype(np.float32)

@@ -54,9 +54,11 @@ __global__ void __launch_bounds__(kWave) q_tree_kernel(LeafTreeArgs<T> a, int le
         constexpr int J = NC - 1 - decltype(jc)::value;
         const int tix = lane < NC ? J + lane * NC : NC * NC;    // lanes past NC: the spare cell
         const T t = tau[J];
-        T w = Qt[tix];
+        // four partial sums shorten the dependent chain of the dot product
+        T wp[4] = {Qt[tix], T(0), T(0), T(0)};
 #pragma unroll
-        for (int i = 0; i <= J; ++i) w = fmadd(Vl[Tri<NC>::off(i) + J - i], qb[i], w);
+        for (int i = 0; i <= J; ++i) wp[i & 3] = fmadd(Vl[Tri<NC>::off(i) + J - i], qb[i], wp[i & 3]);
+        const T w = (wp[0] + wp[1]) + (wp[2] + wp[3]);
         const T tw = t * w;
         Qt[tix] = Qt[tix] - tw;
 #pragma unroll
