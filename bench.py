@@ -9,10 +9,12 @@ which launches a small kernel that clears the tree counters and then the fused
 leaf+tree kernel.  Prints ONE JSON line on stdout; progress goes to stderr.
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 30] [--no-cpu-baseline] [--no-batched]
-        [--no-mixed] [--no-q] [--no-library]
+        [--no-mixed] [--no-q] [--no-library] [--no-tuning]
 
 The warmup is long enough (about 50 ms of kernel time) for the GPU clocks to
-settle before the timed steps.
+settle before the timed steps.  The handle follows the shipped tuning table
+(paper_1002_4250_amd/tuning_gfx950.json, written by the autotuner); at the
+benchmark's shapes it selects the built-in defaults.
 
 The ``mixed`` object measures 256 FP32-stored instances of 2^16 x 50 with
 condition numbers 1..1e8: FP32 TSQR followed by one FP64 correction, against
@@ -331,6 +333,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-q", action="store_true")
     ap.add_argument("--no-library", action="store_true", help="skip timing torch.linalg.qr beside the Q factor")
+    ap.add_argument("--no-tuning", action="store_true", help="ignore the shipped tuning table")
     ap.add_argument("--m", type=int, default=1 << 22)
     ap.add_argument("--n", type=int, default=50)
     ap.add_argument("--profile-copy-bytes", type=int, default=0,
@@ -345,13 +348,15 @@ def main():
     import numpy as np
     import torch
 
-    from paper_1002_4250_amd import inputs, tsqr
+    from paper_1002_4250_amd import autotune, inputs, tsqr
 
     if not torch.cuda.is_available():
         log("no GPU available")
         sys.exit(1)
     m, n = args.m, args.n
     h = tsqr.handle(0)
+    # the launch configuration measured by the autotuner (paper_1002_4250_amd/tuning_gfx950.json)
+    tuned = 0 if args.no_tuning else autotune.apply_default(h)
     leaf_rows, leaves = tsqr.tsqr_plan_info(h, m, n, tsqr.TSQR_F64)
     log(f"workload m={m} n={n} fp64: {leaves} leaves of {leaf_rows} rows")
 
@@ -421,7 +426,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"tsqr_r_factor m={m} n={n} fp64 uniform[-1,1) seed 1, one instance per step",
-                   "m": m, "n": n, "leaves": leaves, "leaf_rows": leaf_rows, "parallelism": "single GPU"},
+                   "m": m, "n": n, "leaves": leaves, "leaf_rows": leaf_rows, "parallelism": "single GPU",
+                   "tuning_table_entries": tuned},
         "roofline": {"bound": "alu", "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": tflops / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "kernel": "tsqr_leaf_tree_kernel<double,50>", "kernel_ms": ms_kernel,

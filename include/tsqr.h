@@ -94,6 +94,35 @@ const char *tsqr_status_string(int status);
 /* Set a tuning option (see TSQR_OPT_*).  Negative values are rejected. */
 int tsqr_set_option(tsqr_handle_t handle, int option, int64_t value);
 
+/* ---- tuning table ---------------------------------------------------------------
+ *
+ * The launch configuration that the automatic policy uses can come from a
+ * table measured on the device (paper_1002_4250_amd/autotune.py writes one).
+ * An entry applies to calls of element type `dtype` whose column count pads to
+ * the same compiled width as `n`:
+ *   batch == 0: single-matrix calls (tsqr_geqr_r_*, tsqr_plan_info,
+ *               tsqr_workspace_bytes, tsqr_geqr_qr_f64) with m <= m_max; of
+ *               several such entries the one with the smallest m_max wins;
+ *   batch != 0: batched plans (m_max is ignored).
+ * It sets the rows per lane (a compiled value for that width; the Q-factor
+ * entry point keeps its fixed 8) and the leaf size: `leaf_rows` if positive,
+ * else `waves_per_cu` leaves per compute unit if positive, else the built-in
+ * policy.  Options set with tsqr_set_option take precedence over the table.
+ * An entry with the same key (dtype, width, batch, and m_max for single-matrix
+ * entries) replaces the earlier one.  Host-only; changes plans made after the
+ * call, not existing batched plans.  Argument codes: -1 handle, -2 dtype,
+ * -3 n (not in 1..TSQR_MAX_N), -4 m_max, -5 rows_per_lane (not compiled for
+ * this width), -6 waves_per_cu, -7 leaf_rows; TSQR_ERR_UNSUPPORTED once the
+ * table holds 4096 entries. */
+int tsqr_tuning_add(tsqr_handle_t handle, int dtype, int64_t n, int64_t m_max, int64_t rows_per_lane,
+                    int64_t waves_per_cu, int64_t leaf_rows, int batch);
+/* Remove every entry of the handle's tuning table. */
+int tsqr_tuning_clear(tsqr_handle_t handle);
+/* The rows-per-lane values compiled for (dtype, width of n): writes up to
+ * `capacity` of them to the host array `values` and returns how many exist;
+ * -1 dtype, -2 n, -3 values/capacity. */
+int64_t tsqr_rows_per_lane_compiled(int dtype, int64_t n, int64_t *values, int64_t capacity);
+
 /* Launch geometry tsqr_geqr_r_* will use for (m, n, dtype): rows per leaf and
  * number of leaves (workgroups).  Either output pointer may be NULL. */
 int tsqr_plan_info(tsqr_handle_t handle, int64_t m, int64_t n, int dtype,
@@ -157,7 +186,8 @@ int tsqr_qr_uppers_f32(tsqr_handle_t handle, int64_t n, float *R1, float *R2, fl
  * the m[b]-by-n column-major matrix at element offset a_offset[b] of the A
  * pointer given to tsqr_batch_exec, with leading dimension lda[b] (NULL:
  * lda[b] = max(1, m[b])).  The leaf size is the handle's TSQR_OPT_LEAF_ROWS if
- * set, else 64 chunks.  The plan allocates two small device tables (freed by
+ * set, else the tuning table's batched entry, else 64 chunks; rows per lane
+ * likewise (option, table, built-in default).  The plan allocates two small device tables (freed by
  * tsqr_batch_plan_destroy) and keeps a pointer to the handle, which must
  * outlive it.  Argument codes: -1 handle, -2 batch, -3 n, -4 m, -5 a_offset,
  * -6 lda, -7 dtype, -8 plan. */

@@ -12,6 +12,18 @@
 
 #include "tsqr_internal.h"
 
+// One row of the tuning table: the launch configuration the automatic policy
+// uses for one element type, one compiled column width and a range of m.
+struct TuneEntry {
+    int dtype;
+    int nc;                // compiled column width the entry applies to
+    int64_t m_max;         // applies to m <= m_max (the smallest such entry wins); batched entries ignore it
+    int rpl;               // rows per lane
+    int64_t waves_per_cu;  // leaves per compute unit (0 = as many as are resident)
+    int64_t leaf_rows;     // explicit leaf size (0 = from waves_per_cu)
+    bool batch;            // an entry for batched plans
+};
+
 struct tsqr_handle_s {
     int device;
     int cu_count;
@@ -20,6 +32,7 @@ struct tsqr_handle_s {
     int64_t waves_per_cu;  // leaves per compute unit targeted by the automatic policy
     int last_hip_error;
     bool planning_only;    // no device: checks and planning only
+    std::vector<TuneEntry> tuning;
 };
 
 namespace {
@@ -71,15 +84,31 @@ int leaf_occupancy(const tsqr_handle_s* h, int dtype, int nc, int rpl)
     return occ > 0 ? occ : 4;
 }
 
+// The tuning-table entry for a call: the smallest m_max >= m among the
+// single-matrix entries, or the batched entry; NULL if none applies.
+const TuneEntry* find_tuning(const tsqr_handle_s* h, int dtype, int nc, int64_t m, bool batch)
+{
+    const TuneEntry* best = nullptr;
+    for (const TuneEntry& e : h->tuning) {
+        if (e.dtype != dtype || e.nc != nc || e.batch != batch) continue;
+        if (batch) return &e;
+        if (m <= e.m_max && (!best || e.m_max < best->m_max)) best = &e;
+    }
+    return best;
+}
+
 // Leaf policy: a chunk is 16*RPL rows; the automatic leaf size gives
 // waves_per_cu leaves per compute unit (each leaf is one wavefront; by default
 // as many as are resident at once), never less than one chunk.  The tree then
-// has ceil(log2 P) levels.
-int plan(const tsqr_handle_s* h, int64_t m, int64_t n, int dtype, Geometry* g)
+// has ceil(log2 P) levels.  Options set on the handle take precedence over
+// the tuning table, which takes precedence over the built-in defaults.
+int plan(const tsqr_handle_s* h, int64_t m, int64_t n, int dtype, Geometry* g, bool batch = false)
 {
     g->nc = padded_columns(n);
     if (g->nc < 0) return TSQR_ERR_UNSUPPORTED;
-    g->rpl = (int)(h->rpl > 0 ? h->rpl : (dtype == TSQR_F64 ? TSQR_DEFAULT_RPL_F64 : TSQR_DEFAULT_RPL_F32));
+    const TuneEntry* te = find_tuning(h, dtype, g->nc, m, batch);
+    g->rpl = (int)(h->rpl > 0 ? h->rpl
+                              : (te ? te->rpl : (dtype == TSQR_F64 ? TSQR_DEFAULT_RPL_F64 : TSQR_DEFAULT_RPL_F32)));
     if (!leaf_instance_exists(dtype, g->nc, g->rpl)) {
         // fall back to the default rows-per-lane, else any compiled one, for this column count
         g->rpl = dtype == TSQR_F64 ? TSQR_DEFAULT_RPL_F64 : TSQR_DEFAULT_RPL_F32;
@@ -96,8 +125,18 @@ int plan(const tsqr_handle_s* h, int64_t m, int64_t n, int dtype, Geometry* g)
     int64_t L;
     if (h->leaf_rows > 0) {
         L = align_up(h->leaf_rows, chunk);
+    } else if (te && te->leaf_rows > 0) {
+        L = align_up(te->leaf_rows, chunk);
+    } else if (batch) {
+        // batched leaves: 64 chunks (8192 rows at 8 rows per lane).  Leaves
+        // that long keep most instances of a ragged batch in a single leaf,
+        // with no tree at all, and give the large ones shallow trees; the
+        // many instances supply the parallelism.
+        L = 64 * chunk;
     } else {
-        const int64_t wpc = h->waves_per_cu > 0 ? h->waves_per_cu : leaf_occupancy(h, dtype, g->nc, g->rpl);
+        const int64_t wpc = h->waves_per_cu > 0 ? h->waves_per_cu
+                            : (te && te->waves_per_cu > 0) ? te->waves_per_cu
+                                                           : leaf_occupancy(h, dtype, g->nc, g->rpl);
         const int64_t target = (int64_t)h->cu_count * wpc;
         L = (m + target - 1) / (target > 0 ? target : 1);
         L = align_up(L > chunk ? L : chunk, chunk);
@@ -294,6 +333,65 @@ int tsqr_set_option(tsqr_handle_t handle, int option, int64_t value)
     }
 }
 
+int tsqr_tuning_add(tsqr_handle_t handle, int dtype, int64_t n, int64_t m_max, int64_t rows_per_lane,
+                    int64_t waves_per_cu, int64_t leaf_rows, int batch)
+{
+    if (!handle) return -1;
+    if (dtype != TSQR_F64 && dtype != TSQR_F32) return -2;
+    const int nc = n >= 1 ? padded_columns(n) : -1;
+    if (nc < 0) return -3;
+    if (m_max < 0) return -4;
+    if (rows_per_lane < 1 || rows_per_lane > 64 || !leaf_instance_exists(dtype, nc, (int)rows_per_lane)) return -5;
+    if (waves_per_cu < 0) return -6;
+    if (leaf_rows < 0) return -7;
+    if (handle->tuning.size() >= 4096) return TSQR_ERR_UNSUPPORTED;
+    TuneEntry e;
+    e.dtype = dtype;
+    e.nc = nc;
+    e.m_max = m_max;
+    e.rpl = (int)rows_per_lane;
+    e.waves_per_cu = waves_per_cu;
+    e.leaf_rows = leaf_rows;
+    e.batch = batch != 0;
+    // a later entry for the same key replaces the earlier one
+    for (TuneEntry& old : handle->tuning) {
+        if (old.dtype == e.dtype && old.nc == e.nc && old.batch == e.batch && (e.batch || old.m_max == e.m_max)) {
+            old = e;
+            return 0;
+        }
+    }
+    try {
+        handle->tuning.push_back(e);
+    } catch (...) {
+        return TSQR_ERR_ALLOC;
+    }
+    return 0;
+}
+
+int tsqr_tuning_clear(tsqr_handle_t handle)
+{
+    if (!handle) return -1;
+    handle->tuning.clear();
+    return 0;
+}
+
+int64_t tsqr_rows_per_lane_compiled(int dtype, int64_t n, int64_t* values, int64_t capacity)
+{
+    if (dtype != TSQR_F64 && dtype != TSQR_F32) return -1;
+    const int nc = n >= 1 ? padded_columns(n) : -1;
+    if (nc < 0) return -2;
+    if (capacity < 0 || (capacity > 0 && !values)) return -3;
+    int64_t count = 0;
+#define TSQR_LIST(tag, NC, RPL)                                                 \
+    if ((dtype == TSQR_F64) == (sizeof(tsqr::tag) == 8) && nc == NC) {          \
+        if (count < capacity) values[count] = RPL;                              \
+        ++count;                                                                \
+    }
+    TSQR_LEAF_INSTANCES(TSQR_LIST)
+#undef TSQR_LIST
+    return count;
+}
+
 int tsqr_plan_info(tsqr_handle_t handle, int64_t m, int64_t n, int dtype, int64_t* leaf_rows, int64_t* leaves)
 {
     if (!handle) return -1;
@@ -380,14 +478,12 @@ int tsqr_batch_plan_create(tsqr_handle_t h, int64_t batch, int64_t n, const int6
     }
     if (n > TSQR_MAX_N) return TSQR_ERR_UNSUPPORTED;
     Geometry g;
-    int rc = n > 0 ? plan(h, 1, n, dtype, &g) : 0;
+    int rc = n > 0 ? plan(h, 1, n, dtype, &g, true) : 0;
     if (rc) return rc;
-    const int64_t chunk = (int64_t)kRowsPerLaneUnit * (n > 0 ? g.rpl : 1);
-    // batched leaves: the handle's leaf size if set, else 64 chunks (8192
-    // rows at 8 rows per lane).  Leaves that long keep most instances of a
-    // ragged batch in a single leaf, with no tree at all, and give the large
-    // ones shallow trees; the many instances supply the parallelism.
-    const int64_t L = h->leaf_rows > 0 ? align_up(h->leaf_rows, chunk) : 64 * chunk;
+    // the leaf size: the handle's option, else the tuning table's batched
+    // entry, else 64 chunks (see plan)
+    const int64_t L = n > 0 ? g.leaf_rows
+                            : (h->leaf_rows > 0 ? align_up(h->leaf_rows, kRowsPerLaneUnit) : 64 * kRowsPerLaneUnit);
     std::vector<tsqr::BatchInstance> inst((size_t)batch);
     std::vector<tsqr::BatchTile> tiles;
     std::vector<int64_t> tile_rows;

@@ -38,6 +38,9 @@ SIGNATURES = [
     ("tsqr_status_string", ctypes.c_char_p, [_i]),
     ("tsqr_set_option", _i, [_p, _i, _i64]),
     ("tsqr_plan_info", _i, [_p, _i64, _i64, _i, _pi64, _pi64]),
+    ("tsqr_tuning_add", _i, [_p, _i, _i64, _i64, _i64, _i64, _i64, _i]),
+    ("tsqr_tuning_clear", _i, [_p]),
+    ("tsqr_rows_per_lane_compiled", _i64, [_i, _i64, _pi64, _i64]),
     ("tsqr_workspace_bytes", _i64, [_p, _i64, _i64, _i]),
     ("tsqr_geqr_r_f64", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
     ("tsqr_geqr_r_f32", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
@@ -126,6 +129,27 @@ def tsqr_plan_info(handle: int, m: int, n: int, dtype: int):
     return lr.value, lv.value
 
 
+def tsqr_tuning_add(handle: int, dtype: int, n: int, m_max: int, rows_per_lane: int, waves_per_cu: int,
+                    leaf_rows: int, batch: bool) -> None:
+    _check("tsqr_tuning_add", lib().tsqr_tuning_add(handle, int(dtype), int(n), int(m_max), int(rows_per_lane),
+                                                    int(waves_per_cu), int(leaf_rows), int(bool(batch))), handle)
+
+
+def tsqr_tuning_clear(handle: int) -> None:
+    _check("tsqr_tuning_clear", lib().tsqr_tuning_clear(handle), handle)
+
+
+def tsqr_rows_per_lane_compiled(dtype: int, n: int) -> list:
+    count = lib().tsqr_rows_per_lane_compiled(int(dtype), int(n), None, 0)
+    if count < 0:
+        raise TsqrError("tsqr_rows_per_lane_compiled", int(count))
+    buf = (ctypes.c_int64 * max(int(count), 1))()
+    got = lib().tsqr_rows_per_lane_compiled(int(dtype), int(n), buf, int(count))
+    if got != count:
+        raise TsqrError("tsqr_rows_per_lane_compiled", int(got))
+    return [int(buf[i]) for i in range(count)]
+
+
 def tsqr_workspace_bytes(handle: int, m: int, n: int, dtype: int) -> int:
     v = lib().tsqr_workspace_bytes(handle, int(m), int(n), int(dtype))
     if v < 0:
@@ -179,6 +203,42 @@ def _col_major(A):
     return m, n, lda
 
 
+def _check_matrix(X, name, rows, cols, dtype, dev):
+    """X must be a rows x cols column-major tensor of `dtype` on `dev` (the
+    kernels take raw pointers, so a wrong output tensor is refused here);
+    returns its leading dimension."""
+    if X.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {X.dtype}")
+    if X.device != dev:
+        raise ValueError(f"{name} must be on {dev}, got {X.device}")
+    if tuple(X.shape) != (rows, cols):
+        raise ValueError(f"{name} must have shape ({rows}, {cols}), got {tuple(X.shape)}")
+    if rows > 1 and X.stride(0) != 1:
+        raise ValueError(f"{name} must be column-major (stride(0) == 1)")
+    ld = X.stride(1) if cols > 1 else max(rows, 1)
+    if ld < max(rows, 1):
+        raise ValueError(f"{name} has a leading dimension below its row count")
+    return ld
+
+
+def _check_flat(X, name, numel, dtype, dev):
+    """X must be a contiguous tensor of `dtype` on `dev` with at least `numel` elements."""
+    if X.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {X.dtype}")
+    if X.device != dev:
+        raise ValueError(f"{name} must be on {dev}, got {X.device}")
+    if not X.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if X.numel() < numel:
+        raise ValueError(f"{name} needs at least {numel} elements, has {X.numel()}")
+
+
+def _ws_bytes(ws, dev):
+    if ws.device != dev or not ws.is_contiguous():
+        raise ValueError("the workspace must be a contiguous tensor on the matrix's device")
+    return ws.numel() * ws.element_size()
+
+
 def workspace(m: int, n: int, dtype, device=None, h=None):
     """A uint8 workspace tensor large enough for geqr_r(m, n) with the
     handle's current options."""
@@ -203,11 +263,12 @@ def geqr_r(A, R=None, ws=None, h=None):
     h = h or handle(dev.index or 0)
     if R is None:
         R = torch.empty((n, n), dtype=A.dtype, device=dev).t()   # column-major n x n
-    ldr = R.stride(1) if n > 1 else max(n, 1)
+    ldr = _check_matrix(R, "R", n, n, A.dtype, dev)
     if ws is None:
         ws = workspace(m, n, A.dtype, dev, h)
     fn = tsqr_geqr_r_f64 if A.dtype == torch.float64 else tsqr_geqr_r_f32
-    st = fn(h, m, n, A.data_ptr(), lda, R.data_ptr(), ldr, ws.data_ptr(), ws.numel(), _stream_ptr(torch, dev))
+    st = fn(h, m, n, A.data_ptr(), lda, R.data_ptr(), ldr, ws.data_ptr(), _ws_bytes(ws, dev),
+            _stream_ptr(torch, dev))
     _check(fn.__name__, st, h)
     return R
 
@@ -217,12 +278,17 @@ def qr_uppers(R1, R2, tau=None, h=None):
     R1 <- R, R2 <- V, tau <- reflector scalars.  Returns (R1, R2, tau)."""
     import torch
     n = R1.shape[0]
+    if R1.dtype not in (torch.float64, torch.float32) or not R1.is_cuda:
+        raise TypeError("R1 must be a float64 or float32 device tensor")
     for X in (R1, R2):
         if X.shape != (n, n) or (n > 1 and X.stride() != (1, n)):
             raise ValueError("R1 and R2 must be n-by-n column-major with leading dimension n")
+        if X.dtype != R1.dtype or X.device != R1.device:
+            raise TypeError("R1 and R2 must have the same dtype and device")
     h = h or handle(R1.device.index or 0)
     if tau is None:
         tau = torch.empty(max(n, 1), dtype=R1.dtype, device=R1.device)
+    _check_flat(tau, "tau", n, R1.dtype, R1.device)
     fn = tsqr_qr_uppers_f64 if R1.dtype == torch.float64 else tsqr_qr_uppers_f32
     st = fn(h, n, R1.data_ptr(), R2.data_ptr(), tau.data_ptr(), _stream_ptr(torch, R1.device))
     _check(fn.__name__, st, h)
@@ -288,6 +354,8 @@ class BatchPlan:
         self.batch = len(sizes)
         self.dtype = dtype
         code = TSQR_F64 if dtype == torch.float64 else TSQR_F32
+        # elements of A the instances span (column-major, lda = m)
+        self.a_elems = max([int(o) + int(m) * self.n for m, o in zip(sizes, offsets)] + [0])
         self.plan = tsqr_batch_plan_create(self.h, self.batch, self.n, sizes, offsets, None, code)
         nbytes = max(tsqr_batch_workspace_bytes(self.plan), 256)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.dev)
@@ -297,8 +365,10 @@ class BatchPlan:
 
     def run(self, A_flat, R=None):
         torch = self.torch
+        _check_flat(A_flat, "A", self.a_elems, self.dtype, self.dev)
         if R is None:
             R = torch.empty((self.batch, self.n, self.n), dtype=self.dtype, device=self.dev)
+        _check_flat(R, "R", self.batch * self.n * self.n, self.dtype, self.dev)
         st = tsqr_batch_exec(self.plan, A_flat.data_ptr(), R.data_ptr(), self.n, self.ws.data_ptr(),
                              self.ws.numel(), _stream_ptr(torch, self.dev))
         _check("tsqr_batch_exec", st, self.h)
@@ -352,16 +422,18 @@ class MixedPlan:
         self.batch, self.m, self.n = int(batch), int(m), int(n)
         lda = max(self.m, 1) if lda is None else int(lda)
         stride = lda * self.n if stride is None else int(stride)
+        # elements of A the instances span
+        self.a_elems = (self.batch - 1) * stride + (self.n - 1) * lda + self.m if self.batch and self.n and self.m else 0
         self.plan = tsqr_mixed_plan_create(self.h, self.batch, self.m, self.n, lda, stride)
         nbytes = max(tsqr_mixed_workspace_bytes(self.plan), 256)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.dev)
 
     def run(self, A_flat, R=None):
         torch = self.torch
-        if A_flat.dtype != torch.float32:
-            raise TypeError("A must be float32")
+        _check_flat(A_flat, "A", self.a_elems, torch.float32, self.dev)
         if R is None:
             R = torch.empty((self.batch, self.n, self.n), dtype=torch.float64, device=self.dev)
+        _check_flat(R, "R", self.batch * self.n * self.n, torch.float64, self.dev)
         fb = (ctypes.c_int * max(self.batch, 1))()
         st = tsqr_mixed_exec(self.plan, A_flat.data_ptr(), R.data_ptr(), self.n, fb, self.ws.data_ptr(),
                              self.ws.numel(), _stream_ptr(torch, self.dev))
@@ -397,6 +469,8 @@ def geqr_qr(A, Q=None, R=None, ws=None, h=None):
     import torch
     if A.dtype != torch.float64:
         raise TypeError("A must be float64")
+    if not A.is_cuda:
+        raise ValueError("A must be a device tensor")
     m, n, lda = _col_major(A)
     dev = A.device
     h = h or handle(dev.index or 0)
@@ -404,11 +478,11 @@ def geqr_qr(A, Q=None, R=None, ws=None, h=None):
         Q = torch.empty((n, m), dtype=A.dtype, device=dev).t()
     if R is None:
         R = torch.empty((n, n), dtype=A.dtype, device=dev).t()
-    ldq = Q.stride(1) if n > 1 else max(m, 1)
-    ldr = R.stride(1) if n > 1 else max(n, 1)
+    ldq = _check_matrix(Q, "Q", m, n, A.dtype, dev)
+    ldr = _check_matrix(R, "R", n, n, A.dtype, dev)
     if ws is None:
         ws = torch.empty(max(tsqr_qr_workspace_bytes(h, m, n), 256), dtype=torch.uint8, device=dev)
     st = tsqr_geqr_qr_f64(h, m, n, A.data_ptr(), lda, Q.data_ptr(), ldq, R.data_ptr(), ldr, ws.data_ptr(),
-                          ws.numel(), _stream_ptr(torch, dev))
+                          _ws_bytes(ws, dev), _stream_ptr(torch, dev))
     _check("tsqr_geqr_qr_f64", st, h)
     return Q, R

@@ -261,3 +261,107 @@ def test_qr_workspace_query(ph):
     need = tsqr.tsqr_qr_workspace_bytes(ph, m, n)
     assert need >= r_only + 8 * m * n
     assert L.tsqr_geqr_qr_f64(ph, m, n, 1, m, 1, m, 1, n, None, need, None) == -10
+
+
+def test_tuning_table_steers_the_automatic_policy(ph):
+    F64, F32 = tsqr.TSQR_F64, tsqr.TSQR_F32
+    base = {m: tsqr.tsqr_plan_info(ph, m, 50, F64) for m in (1 << 16, 1 << 18, 1 << 20, 1 << 21)}
+    # m <= 2^20: rows per lane 8, 8 leaves per compute unit
+    tsqr.tsqr_tuning_add(ph, F64, 50, 1 << 20, 8, 8, 0, False)
+    assert tsqr.tsqr_plan_info(ph, 1 << 20, 50, F64) == (512, 2048)
+    assert tsqr.tsqr_plan_info(ph, 1 << 21, 50, F64) == base[1 << 21]        # above every m_max
+    assert tsqr.tsqr_plan_info(ph, 1 << 20, 50, F32) == tsqr.tsqr_plan_info(ph, 1 << 20, 49, F32)
+    # the smallest m_max that covers m wins; an explicit leaf size is rounded to
+    # the entry's chunk (16 x 4 rows)
+    tsqr.tsqr_tuning_add(ph, F64, 50, 1 << 16, 4, 0, 1000, False)
+    assert tsqr.tsqr_plan_info(ph, 1 << 16, 50, F64) == (1024, 64)
+    assert tsqr.tsqr_plan_info(ph, 1 << 18, 50, F64) == (128, 2048)
+    # every column count that pads to the same compiled width shares the entry
+    assert tsqr.tsqr_plan_info(ph, 1 << 16, 33, F64) == (1024, 64)
+    assert tsqr.tsqr_plan_info(ph, 1 << 16, 16, F64) != (1024, 64)
+    # handle options take precedence over the table
+    tsqr.tsqr_set_option(ph, tsqr.TSQR_OPT_LEAF_ROWS, 256)
+    assert tsqr.tsqr_plan_info(ph, 1 << 16, 50, F64) == (256, 256)
+    tsqr.tsqr_set_option(ph, tsqr.TSQR_OPT_LEAF_ROWS, 0)
+    # an entry with the same key replaces the earlier one
+    tsqr.tsqr_tuning_add(ph, F64, 50, 1 << 16, 8, 0, 2048, False)
+    assert tsqr.tsqr_plan_info(ph, 1 << 16, 50, F64) == (2048, 32)
+    # batched plans take the batched entry (rows per lane 16: 256-row chunks)
+    tsqr.tsqr_tuning_add(ph, F32, 50, 0, 16, 0, 4000, True)
+    p = _batch_create(ph, [5000, 100, 9000], 50, tsqr.TSQR_F32)
+    try:
+        tiles, leaves, L = tsqr.tsqr_batch_plan_info(p)
+        assert L == 4096 and tiles == 2 + 1 + 3
+    finally:
+        tsqr.tsqr_batch_plan_destroy(p)
+    p = _batch_create(ph, [5000], 50, tsqr.TSQR_F64)          # no FP64 batched entry
+    try:
+        assert tsqr.tsqr_batch_plan_info(p)[2] == 64 * 16 * 8
+    finally:
+        tsqr.tsqr_batch_plan_destroy(p)
+    # clearing restores the built-in policy
+    tsqr.tsqr_tuning_clear(ph)
+    for m, g in base.items():
+        assert tsqr.tsqr_plan_info(ph, m, 50, F64) == g
+
+
+def test_tuning_argument_checks(ph):
+    L = tsqr.lib()
+    F64, F32 = tsqr.TSQR_F64, tsqr.TSQR_F32
+    assert L.tsqr_tuning_add(None, F64, 50, 10, 8, 0, 0, 0) == -1
+    assert L.tsqr_tuning_add(ph, 7, 50, 10, 8, 0, 0, 0) == -2
+    assert L.tsqr_tuning_add(ph, F64, 0, 10, 8, 0, 0, 0) == -3
+    assert L.tsqr_tuning_add(ph, F64, 65, 10, 8, 0, 0, 0) == -3
+    assert L.tsqr_tuning_add(ph, F64, 50, -1, 8, 0, 0, 0) == -4
+    assert L.tsqr_tuning_add(ph, F64, 50, 10, 5, 0, 0, 0) == -5       # not compiled
+    assert L.tsqr_tuning_add(ph, F64, 50, 10, 0, 0, 0, 0) == -5
+    assert L.tsqr_tuning_add(ph, F64, 50, 10, 8, -1, 0, 0) == -6
+    assert L.tsqr_tuning_add(ph, F64, 50, 10, 8, 0, -1, 0) == -7
+    assert L.tsqr_tuning_clear(None) == -1
+    assert tsqr.tsqr_rows_per_lane_compiled(F64, 50) == [4, 6, 8]
+    assert tsqr.tsqr_rows_per_lane_compiled(F32, 50) == [8, 12, 16]
+    assert tsqr.tsqr_rows_per_lane_compiled(F64, 9) == [8]
+    assert L.tsqr_rows_per_lane_compiled(7, 50, None, 0) == -1
+    assert L.tsqr_rows_per_lane_compiled(F64, 65, None, 0) == -2
+    assert L.tsqr_rows_per_lane_compiled(F64, 50, None, 1) == -3
+    assert L.tsqr_rows_per_lane_compiled(F64, 50, None, 0) == 3
+
+
+def test_shipped_tuning_table_applies(ph):
+    from paper_1002_4250_amd import autotune
+    table = autotune.load()
+    if table is None:
+        pytest.skip("no tuning table shipped")
+    assert autotune.apply(ph, table) == len(table["entries"]) > 0
+    for e in table["entries"]:
+        # each entry is the fastest of the candidates it records
+        assert e["us"] == min(c[2] for c in e["candidates"]), e["dtype"]
+        assert e["rows_per_lane"] in tsqr.tsqr_rows_per_lane_compiled(autotune.DTYPES[e["dtype"]], e["n"])
+    singles = sorted(e["m_max"] for e in table["entries"] if not e["batch"] and e["dtype"] == "f64")
+    assert singles == sorted(set(singles)) and singles[-1] >= 1 << 40
+
+
+def test_binding_refuses_wrong_tensors():
+    torch = pytest.importorskip("torch")
+    cpu = torch.device("cpu")
+    R = torch.empty((5, 5), dtype=torch.float64).t()
+    assert tsqr._check_matrix(R, "R", 5, 5, torch.float64, cpu) == 5
+    wide = torch.empty((5, 7), dtype=torch.float64).t()[:5, :]     # leading dimension 7
+    assert tsqr._check_matrix(wide, "R", 5, 5, torch.float64, cpu) == 7
+    with pytest.raises(TypeError):
+        tsqr._check_matrix(R.float(), "R", 5, 5, torch.float64, cpu)
+    with pytest.raises(ValueError):
+        tsqr._check_matrix(torch.empty((5, 5), dtype=torch.float64), "R", 5, 5, torch.float64, cpu)  # row-major
+    with pytest.raises(ValueError):
+        tsqr._check_matrix(R[:4, :], "R", 5, 5, torch.float64, cpu)
+    col = torch.empty((3, 8), dtype=torch.float64)[:, 0:1]           # a strided column
+    with pytest.raises(ValueError):
+        tsqr._check_matrix(col, "Q", 3, 1, torch.float64, cpu)
+    flat = torch.empty(100, dtype=torch.float32)
+    tsqr._check_flat(flat, "A", 100, torch.float32, cpu)
+    with pytest.raises(ValueError):
+        tsqr._check_flat(flat, "A", 101, torch.float32, cpu)
+    with pytest.raises(ValueError):
+        tsqr._check_flat(flat[::2], "A", 10, torch.float32, cpu)
+    with pytest.raises(TypeError):
+        tsqr._check_flat(flat, "A", 10, torch.float64, cpu)
