@@ -181,6 +181,25 @@ def time_batched(torch, tsqr, inputs, steps, warmup, n=50, count=4096):
 
     ms_batched = timed(lambda: plan.run(Ad, R), steps, warmup)
     Rb = R.clone()
+    # the batched launch captured in a HIP graph and replayed (checked against the eager result)
+    ms_batched_graph = None
+    try:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            plan.run(Ad, R)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        gb = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gb):
+            plan.run(Ad, R)
+        ms_batched_graph = timed(gb.replay, steps, 2)
+        if not torch.equal(R, Rb):
+            log("batched graph replay differs from the eager launch")
+            ms_batched_graph = None
+        del gb
+    except RuntimeError as e:
+        log(f"graph capture of the batched launch failed: {e}")
 
     # looped single-matrix calls over the same device data, one shared workspace
     h = tsqr.handle(0)
@@ -221,12 +240,15 @@ def time_batched(torch, tsqr, inputs, steps, warmup, n=50, count=4096):
     tflops = flops / (ms_batched * 1e-3) / 1e12
     gbs = 4.0 * sum_rows * n / (ms_batched * 1e-3) / 1e9
     log(f"batched: {ms_batched:.3f} ms/step ({count / ms_batched * 1e3:.0f} instances/s, {tflops:.2f} TFLOP/s); "
+        f"graph replay {ms_batched_graph if ms_batched_graph is None else round(ms_batched_graph, 3)} ms; "
         f"loop {ms_loop:.2f} ms; graph loop {ms_graph if ms_graph is None else round(ms_graph, 3)} ms")
     out = {
         "workload": f"ragged batch {count} instances m log-uniform [64, 65536] (sum {sum_rows}) n={n} fp32 "
                     "uniform[-1,1) seed 2",
         "value": count / (ms_batched * 1e-3), "unit": "instances/s", "ms_per_step": ms_batched,
         "tiles": tiles, "leaf_rows": L,
+        "graph_replay": None if ms_batched_graph is None else
+        {"value": count / (ms_batched_graph * 1e-3), "ms_per_step": ms_batched_graph, "steps": steps},
         "plain_loop": {"value": count / (ms_loop * 1e-3), "ms_per_step": ms_loop, "steps": loop_steps},
         "plain_loop_graph": None if ms_graph is None else
         {"value": count / (ms_graph * 1e-3), "ms_per_step": ms_graph, "steps": loop_steps},
