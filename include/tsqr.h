@@ -213,22 +213,28 @@ int tsqr_batch_exec(tsqr_batch_plan_t plan, const void *A, void *R, int64_t ldr,
 /* ---- the Q factor --------------------------------------------------------------
  *
  * A = Q R with Q m x n with orthonormal columns (column-major, ldq >= m) and R
- * as tsqr_geqr_r_f64 returns it (same leaf size, bit-identical R), m >= n.
- * The factorization keeps every reflector it applies (leaf reflectors, and the
- * V and tau of every merge of the tree, Table 3's outputs), and Q is formed
- * from them: one pass down the tree, one launch per level, then one pass over
- * the leaves (the implicit Q of section 3, made explicit).  Rows per lane are
- * fixed at 8 for this mode (128-row chunks).  A, Q, R and ws are device
- * pointers owned by the caller; the call is asynchronous on `stream` and
- * allocates nothing.  The workspace (256-byte aligned, its size from
- * tsqr_qr_workspace_bytes, which returns a negative code for bad arguments)
- * holds the reflector block, m rounded up to whole chunks by n, so it is about
- * 8mn bytes larger than tsqr_geqr_r's.  Argument codes: -1 handle, -2 m,
- * -3 n (n > m is illegal), -4 A, -5 lda, -6 Q, -7 ldq, -8 R, -9 ldr, -10 ws,
- * -11 ws_bytes; TSQR_ERR_UNSUPPORTED for n > TSQR_MAX_N. */
-int64_t tsqr_qr_workspace_bytes(tsqr_handle_t handle, int64_t m, int64_t n);
+ * as tsqr_geqr_r_f64 / _f32 returns it (same leaf size, bit-identical R),
+ * m >= n.  The factorization keeps every reflector it applies (leaf
+ * reflectors, and the V and tau of every merge of the tree, Table 3's
+ * outputs), and Q is formed from them: one pass down the tree, one launch per
+ * level, then one pass over the leaves (the implicit Q of section 3, made
+ * explicit).  Rows per lane are fixed at 8 for this mode (128-row chunks).
+ * A, Q, R and ws are device pointers owned by the caller; the call is
+ * asynchronous on `stream` and allocates nothing.  The workspace (256-byte
+ * aligned) holds the reflector block, m rounded up to whole chunks by n, so it
+ * is about m*n elements larger than tsqr_geqr_r's.
+ *
+ * tsqr_qr_workspace_bytes: bytes for (m, n, dtype); negative for bad
+ * arguments: -1 handle, -2 m, -3 n (n > m is illegal), -4 dtype, and
+ * -1000 - status for a planning failure.
+ * tsqr_geqr_qr_*: argument codes -1 handle, -2 m, -3 n (n > m is illegal),
+ * -4 A, -5 lda, -6 Q, -7 ldq, -8 R, -9 ldr, -10 ws, -11 ws_bytes;
+ * TSQR_ERR_UNSUPPORTED for n > TSQR_MAX_N. */
+int64_t tsqr_qr_workspace_bytes(tsqr_handle_t handle, int64_t m, int64_t n, int dtype);
 int tsqr_geqr_qr_f64(tsqr_handle_t handle, int64_t m, int64_t n, const double *A, int64_t lda, double *Q,
                      int64_t ldq, double *R, int64_t ldr, void *ws, int64_t ws_bytes, void *stream);
+int tsqr_geqr_qr_f32(tsqr_handle_t handle, int64_t m, int64_t n, const float *A, int64_t lda, float *Q,
+                     int64_t ldq, float *R, int64_t ldr, void *ws, int64_t ws_bytes, void *stream);
 
 /* ---- mixed precision: FP32 TSQR, then one FP64 correction -------------------
  *

@@ -790,8 +790,9 @@ int tsqr_mixed_exec(tsqr_mixed_plan_t plan, const float* A, double* R, int64_t l
     return 0;
 }
 
-// ---- the Q factor (FP64) ----------------------------------------------------
+// ---- the Q factor ------------------------------------------------------------
 
+extern "C++" {
 namespace {
 constexpr int kQrRpl = 8;    // rows per lane of the compiled Q-factor kernels
 
@@ -803,27 +804,28 @@ struct QrLayout {
     int levels;
 };
 
-int qr_plan(const tsqr_handle_s* h, int64_t m, int64_t n, QrLayout* L)
+int qr_plan(const tsqr_handle_s* h, int64_t m, int64_t n, int dtype, QrLayout* L)
 {
     tsqr_handle_s tmp = *h;
     tmp.rpl = kQrRpl;
-    int rc = plan(&tmp, m, n, TSQR_F64, &L->g);
+    int rc = plan(&tmp, m, n, dtype, &L->g);
     if (rc) return rc;
     if (L->g.rpl != kQrRpl) return TSQR_ERR_UNSUPPORTED;
+    const int64_t w = elem_bytes(dtype);
     const int64_t nc = L->g.nc, P = L->g.leaves, CH = (int64_t)kRowsPerLaneUnit * kQrRpl;
     L->nchunks = m > 0 ? (m + CH - 1) / CH : 1;
     int64_t off = L->g.ws_bytes;
     L->ldv = L->nchunks * CH;
     L->off_v = off;
-    off += align_up(L->ldv * n * 8, kAlign);
+    off += align_up(L->ldv * n * w, kAlign);
     L->off_tau_leaf = off;
-    off += align_up(L->nchunks * nc * 8, kAlign);
+    off += align_up(L->nchunks * nc * w, kAlign);
     L->off_vn = off;
-    off += align_up(P * L->g.tri_elems * 8, kAlign);
+    off += align_up(P * L->g.tri_elems * w, kAlign);
     L->off_tau_node = off;
-    off += align_up(P * nc * 8, kAlign);
+    off += align_up(P * nc * w, kAlign);
     L->off_qblk = off;
-    off += align_up(P * nc * nc * 8, kAlign);
+    off += align_up(P * nc * nc * w, kAlign);
     L->ws_bytes = off;
     int levels = 0;
     while (((int64_t)1 << levels) < P) ++levels;
@@ -831,20 +833,22 @@ int qr_plan(const tsqr_handle_s* h, int64_t m, int64_t n, QrLayout* L)
     return 0;
 }
 
-hipError_t dispatch_qr(const tsqr::LeafTreeArgs<double>& a, int nc, double* Q, int64_t ldq, int levels,
-                       hipStream_t s)
+template <typename T>
+hipError_t dispatch_qr(const tsqr::LeafTreeArgs<T>& a, int nc, T* Q, int64_t ldq, int levels, hipStream_t s)
 {
     hipError_t e = hipErrorInvalidValue;
 #define TSQR_CALL(tag, NC, RPL)                                                                          \
-    if constexpr (sizeof(tsqr::tag) == 8) {                                                              \
+    if constexpr (sizeof(T) == sizeof(tsqr::tag)) {                                                      \
         if (nc == NC) {                                                                                  \
-            e = tsqr::launch_qr_leaf_tree_##tag##_##NC##_##RPL(a, s);                                    \
+            const auto& at = reinterpret_cast<const tsqr::LeafTreeArgs<tsqr::tag>&>(a);                  \
+            tsqr::tag* Qt = reinterpret_cast<tsqr::tag*>(Q);                                             \
+            e = tsqr::launch_qr_leaf_tree_##tag##_##NC##_##RPL(at, s);                                   \
             for (int lv = levels - 1; lv >= 0 && e == hipSuccess; --lv) {                                \
                 const int64_t span = (int64_t)1 << lv;                                                   \
-                const int64_t nodes = a.leaves > span ? (a.leaves - 1 - span) / (2 * span) + 1 : 0;      \
-                e = tsqr::launch_q_tree_##tag##_##NC##_##RPL(a, lv, (int)nodes, s);                       \
+                const int64_t nodes = at.leaves > span ? (at.leaves - 1 - span) / (2 * span) + 1 : 0;    \
+                e = tsqr::launch_q_tree_##tag##_##NC##_##RPL(at, lv, (int)nodes, s);                      \
             }                                                                                            \
-            if (e == hipSuccess) e = tsqr::launch_q_leaf_##tag##_##NC##_##RPL(a, Q, ldq, s);             \
+            if (e == hipSuccess) e = tsqr::launch_q_leaf_##tag##_##NC##_##RPL(at, Qt, ldq, s);           \
             return e;                                                                                    \
         }                                                                                                \
     }
@@ -852,23 +856,12 @@ hipError_t dispatch_qr(const tsqr::LeafTreeArgs<double>& a, int nc, double* Q, i
 #undef TSQR_CALL
     return e;
 }
-}  // namespace
 
-int64_t tsqr_qr_workspace_bytes(tsqr_handle_t handle, int64_t m, int64_t n)
+template <typename T>
+int geqr_qr(tsqr_handle_t handle, int64_t m, int64_t n, const T* A, int64_t lda, T* Q, int64_t ldq, T* R,
+            int64_t ldr, void* ws, int64_t ws_bytes, void* stream)
 {
-    if (!handle) return -1;
-    if (m < 0) return -2;
-    if (n < 0 || n > m) return -3;
-    if (n == 0) return 0;
-    QrLayout L;
-    const int rc = qr_plan(handle, m, n, &L);
-    if (rc) return -1000 - rc;
-    return L.ws_bytes;
-}
-
-int tsqr_geqr_qr_f64(tsqr_handle_t handle, int64_t m, int64_t n, const double* A, int64_t lda, double* Q,
-                     int64_t ldq, double* R, int64_t ldr, void* ws, int64_t ws_bytes, void* stream)
-{
+    constexpr int dtype = sizeof(T) == 8 ? TSQR_F64 : TSQR_F32;
     if (!handle) return -1;
     if (m < 0) return -2;
     if (n < 0 || n > m) return -3;
@@ -881,7 +874,7 @@ int tsqr_geqr_qr_f64(tsqr_handle_t handle, int64_t m, int64_t n, const double* A
     if (n == 0) return 0;
     if (n > TSQR_MAX_N) return TSQR_ERR_UNSUPPORTED;
     QrLayout L;
-    int rc = qr_plan(handle, m, n, &L);
+    int rc = qr_plan(handle, m, n, dtype, &L);
     if (rc) return rc;
     if (!ws || (reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) != 0) return -10;
     if (ws_bytes < L.ws_bytes) return -11;
@@ -891,25 +884,52 @@ int tsqr_geqr_qr_f64(tsqr_handle_t handle, int64_t m, int64_t n, const double* A
     unsigned* tickets = reinterpret_cast<unsigned*>(base);
     hipError_t e = tsqr::launch_zero_u32(tickets, L.g.leaves, s);
     if (e != hipSuccess) return hip_status(handle, e);
-    tsqr::LeafTreeArgs<double> a;
+    tsqr::LeafTreeArgs<T> a;
     a.A = A;
     a.m = m;
     a.lda = lda;
     a.n = (int)n;
     a.leaf_rows = L.g.leaf_rows;
     a.leaves = (int)L.g.leaves;
-    a.tri = reinterpret_cast<double*>(base + L.g.ticket_bytes);
+    a.tri = reinterpret_cast<T*>(base + L.g.ticket_bytes);
     a.tickets = tickets;
     a.R = R;
     a.ldr = ldr;
-    a.qs.V = reinterpret_cast<double*>(base + L.off_v);
+    a.qs.V = reinterpret_cast<T*>(base + L.off_v);
     a.qs.ldv = L.ldv;
-    a.qs.tau_leaf = reinterpret_cast<double*>(base + L.off_tau_leaf);
-    a.qs.Vn = reinterpret_cast<double*>(base + L.off_vn);
-    a.qs.tau_node = reinterpret_cast<double*>(base + L.off_tau_node);
-    a.qs.qblk = reinterpret_cast<double*>(base + L.off_qblk);
-    e = dispatch_qr(a, L.g.nc, Q, ldq, L.levels, s);
+    a.qs.tau_leaf = reinterpret_cast<T*>(base + L.off_tau_leaf);
+    a.qs.Vn = reinterpret_cast<T*>(base + L.off_vn);
+    a.qs.tau_node = reinterpret_cast<T*>(base + L.off_tau_node);
+    a.qs.qblk = reinterpret_cast<T*>(base + L.off_qblk);
+    e = dispatch_qr<T>(a, L.g.nc, Q, ldq, L.levels, s);
     return hip_status(handle, e);
+}
+}  // namespace
+}  // extern "C++"
+
+int64_t tsqr_qr_workspace_bytes(tsqr_handle_t handle, int64_t m, int64_t n, int dtype)
+{
+    if (!handle) return -1;
+    if (m < 0) return -2;
+    if (n < 0 || n > m) return -3;
+    if (dtype != TSQR_F64 && dtype != TSQR_F32) return -4;
+    if (n == 0) return 0;
+    QrLayout L;
+    const int rc = qr_plan(handle, m, n, dtype, &L);
+    if (rc) return -1000 - rc;
+    return L.ws_bytes;
+}
+
+int tsqr_geqr_qr_f64(tsqr_handle_t handle, int64_t m, int64_t n, const double* A, int64_t lda, double* Q,
+                     int64_t ldq, double* R, int64_t ldr, void* ws, int64_t ws_bytes, void* stream)
+{
+    return geqr_qr<double>(handle, m, n, A, lda, Q, ldq, R, ldr, ws, ws_bytes, stream);
+}
+
+int tsqr_geqr_qr_f32(tsqr_handle_t handle, int64_t m, int64_t n, const float* A, int64_t lda, float* Q,
+                     int64_t ldq, float* R, int64_t ldr, void* ws, int64_t ws_bytes, void* stream)
+{
+    return geqr_qr<float>(handle, m, n, A, lda, Q, ldq, R, ldr, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

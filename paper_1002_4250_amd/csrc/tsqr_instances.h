@@ -15,7 +15,8 @@
 
 // Q-factor mode: leaf+tree kernel storing reflectors, tree pass, leaf pass
 #define TSQR_QR_INSTANCES(Q) \
-    Q(f64, 16, 8) Q(f64, 32, 8) Q(f64, 50, 8) Q(f64, 64, 8)
+    Q(f64, 16, 8) Q(f64, 32, 8) Q(f64, 50, 8) Q(f64, 64, 8) \
+    Q(f32, 16, 8) Q(f32, 32, 8) Q(f32, 50, 8) Q(f32, 64, 8)
 
 // column counts with a compiled kernel (ascending) and the default rows per lane
 #define TSQR_NC_VALUES 16, 32, 50, 64

@@ -51,8 +51,9 @@ SIGNATURES = [
     ("tsqr_batch_workspace_bytes", _i64, [_p]),
     ("tsqr_batch_plan_info", _i, [_p, _pi64, _pi64, _pi64]),
     ("tsqr_batch_exec", _i, [_p, _p, _p, _i64, _p, _i64, _p]),
-    ("tsqr_qr_workspace_bytes", _i64, [_p, _i64, _i64]),
+    ("tsqr_qr_workspace_bytes", _i64, [_p, _i64, _i64, _i]),
     ("tsqr_geqr_qr_f64", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
+    ("tsqr_geqr_qr_f32", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
     ("tsqr_mixed_plan_create", _i, [_p, _i64, _i64, _i64, _i64, _i64, ctypes.POINTER(_p)]),
     ("tsqr_mixed_plan_destroy", _i, [_p]),
     ("tsqr_mixed_workspace_bytes", _i64, [_p]),
@@ -451,8 +452,8 @@ class MixedPlan:
 
 # ---- the Q factor -----------------------------------------------------------------
 
-def tsqr_qr_workspace_bytes(handle, m, n) -> int:
-    v = lib().tsqr_qr_workspace_bytes(handle, int(m), int(n))
+def tsqr_qr_workspace_bytes(handle, m, n, dtype=TSQR_F64) -> int:
+    v = lib().tsqr_qr_workspace_bytes(handle, int(m), int(n), int(dtype))
     if v < 0:
         raise TsqrError("tsqr_qr_workspace_bytes", int(v) if v > -1000 else int(-1000 - v))
     return int(v)
@@ -462,13 +463,17 @@ def tsqr_geqr_qr_f64(handle, m, n, A, lda, Q, ldq, R, ldr, ws, ws_bytes, stream)
     return lib().tsqr_geqr_qr_f64(handle, m, n, A, lda, Q, ldq, R, ldr, ws, ws_bytes, stream)
 
 
+def tsqr_geqr_qr_f32(handle, m, n, A, lda, Q, ldq, R, ldr, ws, ws_bytes, stream) -> int:
+    return lib().tsqr_geqr_qr_f32(handle, m, n, A, lda, Q, ldq, R, ldr, ws, ws_bytes, stream)
+
+
 def geqr_qr(A, Q=None, R=None, ws=None, h=None):
-    """A = Q R for a column-major float64 device matrix A (m >= n): Q m x n
-    with orthonormal columns, R n x n upper triangular with diag >= 0, both
-    column-major.  Returns (Q, R)."""
+    """A = Q R for a column-major float64 or float32 device matrix A (m >= n):
+    Q m x n with orthonormal columns, R n x n upper triangular with diag >= 0,
+    both column-major.  Returns (Q, R)."""
     import torch
-    if A.dtype != torch.float64:
-        raise TypeError("A must be float64")
+    if A.dtype not in (torch.float64, torch.float32):
+        raise TypeError("A must be float64 or float32")
     if not A.is_cuda:
         raise ValueError("A must be a device tensor")
     m, n, lda = _col_major(A)
@@ -480,9 +485,11 @@ def geqr_qr(A, Q=None, R=None, ws=None, h=None):
         R = torch.empty((n, n), dtype=A.dtype, device=dev).t()
     ldq = _check_matrix(Q, "Q", m, n, A.dtype, dev)
     ldr = _check_matrix(R, "R", n, n, A.dtype, dev)
+    code = TSQR_F64 if A.dtype == torch.float64 else TSQR_F32
     if ws is None:
-        ws = torch.empty(max(tsqr_qr_workspace_bytes(h, m, n), 256), dtype=torch.uint8, device=dev)
-    st = tsqr_geqr_qr_f64(h, m, n, A.data_ptr(), lda, Q.data_ptr(), ldq, R.data_ptr(), ldr, ws.data_ptr(),
-                          _ws_bytes(ws, dev), _stream_ptr(torch, dev))
-    _check("tsqr_geqr_qr_f64", st, h)
+        ws = torch.empty(max(tsqr_qr_workspace_bytes(h, m, n, code), 256), dtype=torch.uint8, device=dev)
+    fn = tsqr_geqr_qr_f64 if A.dtype == torch.float64 else tsqr_geqr_qr_f32
+    st = fn(h, m, n, A.data_ptr(), lda, Q.data_ptr(), ldq, R.data_ptr(), ldr, ws.data_ptr(),
+            _ws_bytes(ws, dev), _stream_ptr(torch, dev))
+    _check(fn.__name__, st, h)
     return Q, R

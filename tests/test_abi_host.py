@@ -252,15 +252,22 @@ def test_mixed_plan_checks_and_workspace(ph):
 
 def test_qr_workspace_query(ph):
     L = tsqr.lib()
-    assert L.tsqr_qr_workspace_bytes(None, 100, 10) == -1
-    assert L.tsqr_qr_workspace_bytes(ph, -1, 10) == -2
-    assert L.tsqr_qr_workspace_bytes(ph, 10, 11) == -3
-    assert L.tsqr_qr_workspace_bytes(ph, 100, 0) == 0
+    F64, F32 = tsqr.TSQR_F64, tsqr.TSQR_F32
+    assert L.tsqr_qr_workspace_bytes(None, 100, 10, F64) == -1
+    assert L.tsqr_qr_workspace_bytes(ph, -1, 10, F64) == -2
+    assert L.tsqr_qr_workspace_bytes(ph, 10, 11, F64) == -3
+    assert L.tsqr_qr_workspace_bytes(ph, 100, 10, 7) == -4
+    assert L.tsqr_qr_workspace_bytes(ph, 100, 0, F64) == 0
+    assert L.tsqr_qr_workspace_bytes(ph, 100, 65, F64) == -1000 - tsqr.TSQR_ERR_UNSUPPORTED
     m, n = 100000, 50
-    r_only = tsqr.tsqr_workspace_bytes(ph, m, n, tsqr.TSQR_F64)
-    need = tsqr.tsqr_qr_workspace_bytes(ph, m, n)
-    assert need >= r_only + 8 * m * n
-    assert L.tsqr_geqr_qr_f64(ph, m, n, 1, m, 1, m, 1, n, None, need, None) == -10
+    for code, w, fn in ((F64, 8, L.tsqr_geqr_qr_f64), (F32, 4, L.tsqr_geqr_qr_f32)):
+        r_only = tsqr.tsqr_workspace_bytes(ph, m, n, code)
+        need = tsqr.tsqr_qr_workspace_bytes(ph, m, n, code)
+        assert need >= r_only + w * m * n and need % 256 == 0
+        assert fn(ph, m, n, 1, m, 1, m, 1, n, None, need, None) == -10
+        assert fn(ph, m, n, 1, m, 1, m, 1, n, 256, need - 1, None) == -11
+        assert fn(ph, m, n, 1, m, 1, m, 1, n, 256, need, None) == tsqr.TSQR_ERR_NO_DEVICE
+    assert tsqr.tsqr_qr_workspace_bytes(ph, m, n, F32) < tsqr.tsqr_qr_workspace_bytes(ph, m, n, F64)
 
 
 def test_tuning_table_steers_the_automatic_policy(ph):

@@ -1,4 +1,5 @@
-"""The Q factor formed from the stored TSQR reflectors (tsqr_geqr_qr_f64).
+"""The Q factor formed from the stored TSQR reflectors (tsqr_geqr_qr_f64 and
+tsqr_geqr_qr_f32).
 
 For A of full column rank, Q with R's diagonal positive is unique:
 Q = A R^-1.  The reference is that definition evaluated on the CPU in FP64
@@ -102,3 +103,44 @@ def test_q_argument_errors():
     assert L.tsqr_geqr_qr_f64(h, 10, 2, 1, 10, 1, 10, 1, 2, None, need, None) == -10
     assert L.tsqr_geqr_qr_f64(h, 10, 2, 1, 10, 1, 10, 1, 2, ws.data_ptr(), need - 1, None) == -11
     assert L.tsqr_geqr_qr_f64(h, 10, 0, None, 10, None, 10, None, 1, None, 0, None) == 0
+
+
+def cond(A):
+    sv = np.linalg.svd(A, compute_uv=False)
+    return float(sv[0] / sv[-1])
+
+
+@pytest.mark.parametrize("m,n,leaf_rows", [(256, 50, 128), (5000, 17, 0), (70000, 50, 1000), (4097, 64, 384),
+                                           (1000, 1, 0), (50, 50, 0)])
+def test_q_fp32_matches_definition(m, n, leaf_rows):
+    """FP32: against the definition on the FP32-rounded input promoted to FP64
+    (the oracle's R), at 1e-5 scaled by the condition number beyond 10 (the
+    batched tests' FP32 gate); Q^T Q = I and Q R = A at FP32 level; R bit for
+    bit the R-only FP32 call with the same leaf size."""
+    A = inputs.uniform(m, n, 31 + n).astype(np.float32)
+    Q, R, Rr = run_qr(A, leaf_rows)
+    assert Q.dtype == np.float32 and R.dtype == np.float32
+    assert np.array_equal(R, Rr)
+    A64 = A.astype(np.float64)
+    Ro = oracle.r_factor(np.asfortranarray(A64))
+    tol = 1e-5 * max(1.0, cond(A64) / 10.0)
+    assert relF(R.astype(np.float64), Ro) < tol
+    Qdef = scipy.linalg.solve_triangular(Ro, A64.T, trans="T", lower=False).T
+    Q64 = Q.astype(np.float64)
+    assert relF(Q64, Qdef) < tol
+    assert np.linalg.norm(Q64.T @ Q64 - np.eye(n)) / np.sqrt(n) < 1e-5
+    assert relF(Q64 @ R.astype(np.float64), A64) < 1e-5
+
+
+def test_q_fp32_argument_errors():
+    h = tsqr.handle(0)
+    L = tsqr.lib()
+    assert L.tsqr_geqr_qr_f32(None, 10, 2, 1, 10, 1, 10, 1, 2, 1, 1 << 20, None) == -1
+    assert L.tsqr_geqr_qr_f32(h, 10, 11, 1, 10, 1, 10, 1, 11, 1, 1 << 20, None) == -3
+    assert L.tsqr_geqr_qr_f32(h, 10, 2, 1, 10, 1, 9, 1, 2, 1, 1 << 20, None) == -7
+    need = tsqr.tsqr_qr_workspace_bytes(h, 10, 2, tsqr.TSQR_F32)
+    ws = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    assert L.tsqr_geqr_qr_f32(h, 10, 2, 1, 10, 1, 10, 1, 2, ws.data_ptr(), need - 1, None) == -11
+    with pytest.raises(TypeError):
+        tsqr.geqr_qr(torch.zeros((10, 2), dtype=torch.float16, device="cuda"))
+
