@@ -102,13 +102,16 @@ const TuneEntry* find_tuning(const tsqr_handle_s* h, int dtype, int nc, int64_t 
 // as many as are resident at once), never less than one chunk.  The tree then
 // has ceil(log2 P) levels.  Options set on the handle take precedence over
 // the tuning table, which takes precedence over the built-in defaults.
-int plan(const tsqr_handle_s* h, int64_t m, int64_t n, int dtype, Geometry* g, bool batch = false)
+// `force_rpl` (if positive) fixes the rows per lane, as the Q-factor mode does.
+int plan(const tsqr_handle_s* h, int64_t m, int64_t n, int dtype, Geometry* g, bool batch = false,
+         int force_rpl = 0)
 {
     g->nc = padded_columns(n);
     if (g->nc < 0) return TSQR_ERR_UNSUPPORTED;
     const TuneEntry* te = find_tuning(h, dtype, g->nc, m, batch);
-    g->rpl = (int)(h->rpl > 0 ? h->rpl
-                              : (te ? te->rpl : (dtype == TSQR_F64 ? TSQR_DEFAULT_RPL_F64 : TSQR_DEFAULT_RPL_F32)));
+    g->rpl = force_rpl > 0 ? force_rpl
+             : (int)(h->rpl > 0 ? h->rpl
+                                : (te ? te->rpl : (dtype == TSQR_F64 ? TSQR_DEFAULT_RPL_F64 : TSQR_DEFAULT_RPL_F32)));
     if (!leaf_instance_exists(dtype, g->nc, g->rpl)) {
         // fall back to the default rows-per-lane, else any compiled one, for this column count
         g->rpl = dtype == TSQR_F64 ? TSQR_DEFAULT_RPL_F64 : TSQR_DEFAULT_RPL_F32;
@@ -806,9 +809,7 @@ struct QrLayout {
 
 int qr_plan(const tsqr_handle_s* h, int64_t m, int64_t n, int dtype, QrLayout* L)
 {
-    tsqr_handle_s tmp = *h;
-    tmp.rpl = kQrRpl;
-    int rc = plan(&tmp, m, n, dtype, &L->g);
+    int rc = plan(h, m, n, dtype, &L->g, false, kQrRpl);
     if (rc) return rc;
     if (L->g.rpl != kQrRpl) return TSQR_ERR_UNSUPPORTED;
     const int64_t w = elem_bytes(dtype);
