@@ -110,7 +110,8 @@ int tsqr_set_option(tsqr_handle_t handle, int option, int64_t value);
  * policy.  Options set with tsqr_set_option take precedence over the table.
  * An entry with the same key (dtype, width, batch, and m_max for single-matrix
  * entries) replaces the earlier one.  Host-only; changes plans made after the
- * call, not existing batched plans.  Argument codes: -1 handle, -2 dtype,
+ * call, not existing batched plans.  Like tsqr_set_option, it must not run
+ * concurrently with other calls on the same handle.  Argument codes: -1 handle, -2 dtype,
  * -3 n (not in 1..TSQR_MAX_N), -4 m_max, -5 rows_per_lane (not compiled for
  * this width), -6 waves_per_cu, -7 leaf_rows; TSQR_ERR_UNSUPPORTED once the
  * table holds 4096 entries. */
