@@ -34,7 +34,7 @@ intensity 2n/8 = 12.5 flop/byte against a ridge of 78.6/8 = 9.8), so
 ``roofline`` reports the kernel's algorithmic 2*m*n^2 flops per launch divided
 by its average launch duration (HIP events on the launch stream) against the
 78.6 TFLOP/s FP64 vector peak.  ``cpu_baseline`` times the CPU oracle (plain
-single-threaded Householder in C) on one full instance.
+single-threaded Householder in C) factoring the full instance twice.
 """
 from __future__ import annotations
 
