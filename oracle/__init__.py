@@ -17,6 +17,8 @@ unless stated):
 * :func:`tsqr_r` -- the method (section 2, Table 1): block QRs then a reduction
   tree of qr_uppers, then sign normalisation.
 * :func:`normalize_signs` -- the positive-diagonal convention (section 2).
+* :func:`q_factor` -- the Q that goes with that R for A of full column rank,
+  by its definition Q = A R^-1 (the Q section 3 leaves implicit); m-by-n.
 """
 from __future__ import annotations
 
@@ -59,6 +61,7 @@ def _lib():
             lib = ctypes.CDLL(build())
             lib.oracle_reflector.argtypes = [_i64, _dp, _dp, _i64, _dp]
             lib.oracle_r_factor.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64]
+            lib.oracle_q_factor.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64]
             lib.oracle_qr_uppers.argtypes = [_i64, _dp, _dp, _dp]
             lib.oracle_tsqr_r.argtypes = [_i64, _i64, _dp, _i64, _i64, ctypes.c_int, _lp, _dp, _i64]
             lib.oracle_normalize_signs.argtypes = [_i64, _dp, _i64]
@@ -94,6 +97,18 @@ def r_factor(A) -> np.ndarray:
         return R
     _check(_lib().oracle_r_factor(m, n, _ptr(A), max(1, m), _ptr(R), max(1, n)), "oracle_r_factor")
     return R
+
+
+def q_factor(A) -> np.ndarray:
+    """Q (m-by-n, orthonormal columns) of A = QR with diag(R) > 0, for A of
+    full column rank (m >= n): the definition Q = A R^-1, R = r_factor(A)."""
+    A = _fortran64(A)
+    m, n = A.shape
+    Q = np.zeros((m, n), dtype=np.float64, order="F")
+    if n == 0:
+        return Q
+    _check(_lib().oracle_q_factor(m, n, _ptr(A), max(1, m), _ptr(Q), max(1, m)), "oracle_q_factor")
+    return Q
 
 
 def reflector(alpha: float, x):

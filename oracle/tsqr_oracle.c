@@ -32,6 +32,11 @@
  *   oracle_normalize_signs -- flip every row whose diagonal entry has its
  *                             sign bit set (section 2, positive-diagonal
  *                             convention).
+ *   oracle_q_factor        -- the plain definition of the Q that goes with
+ *                             that R: for A of full column rank, Q = A R^-1
+ *                             is the unique m-by-n matrix with orthonormal
+ *                             columns and A = QR, diag(R) > 0 (the Q that
+ *                             section 3 notes a reduction leaves implicit).
  *
  * Storage is column-major throughout: element (i, j) of a matrix with leading
  * dimension ld sits at index i + j*ld.  Return value 0 means success; a
@@ -198,6 +203,39 @@ int oracle_r_factor(int64_t m, int64_t n, const double *A, int64_t lda, double *
     oracle_normalize_signs(n, R, ldr);
     free(W);
     free(tau);
+    return 0;
+}
+
+/* The Q of A = QR for A of full column rank with diag(R) > 0: Q = A R^-1 with
+ * R from oracle_r_factor.  Each row q of Q solves q R = a (a the row of A) by
+ * forward substitution over the columns, q_j = (a_j - sum_{i<j} q_i R(i,j)) /
+ * R(j,j), with compensated sums.  Q is m-by-n column-major, ldq >= max(1,m);
+ * m >= n.  Returns 2 if a diagonal entry of R is zero (rank deficient: Q is
+ * not unique) and 1 if memory runs out. */
+int oracle_q_factor(int64_t m, int64_t n, const double *A, int64_t lda, double *Q, int64_t ldq)
+{
+    if (m < 0) return -1;
+    if (n < 0 || n > m) return -2;
+    if (n > 0 && !A) return -3;
+    if (lda < (m > 1 ? m : 1)) return -4;
+    if (n > 0 && !Q) return -5;
+    if (ldq < (m > 1 ? m : 1)) return -6;
+    if (n == 0) return 0;
+    double *R = (double *)malloc(sizeof(double) * (size_t)n * (size_t)n);
+    if (!R) return 1;
+    int rc = oracle_r_factor(m, n, A, lda, R, n);
+    if (rc) { free(R); return rc; }
+    for (int64_t j = 0; j < n; ++j) {
+        if (!(R[IDX(j, j, n)] > 0.0)) { free(R); return 2; }
+    }
+    for (int64_t r = 0; r < m; ++r) {
+        for (int64_t j = 0; j < n; ++j) {
+            csum_t acc = {A[IDX(r, j, lda)], 0.0};
+            for (int64_t i = 0; i < j; ++i) csum_add(&acc, -Q[IDX(r, i, ldq)] * R[IDX(i, j, n)]);
+            Q[IDX(r, j, ldq)] = csum_value(&acc) / R[IDX(j, j, n)];
+        }
+    }
+    free(R);
     return 0;
 }
 

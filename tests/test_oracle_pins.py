@@ -338,3 +338,52 @@ def test_rank_deficient_blocks_stay_finite():
         R = oracle.tsqr_r(A, 1, tree)
         assert np.isfinite(R).all()
         assert relF(R, oracle.r_factor(A)) < 1e-13
+
+
+# ---- the Q factor (definition Q = A R^-1) ------------------------------------------
+
+@pytest.mark.parametrize("m,n,seed", [(300, 7, 3), (1000, 50, 4), (64, 64, 5), (5000, 1, 6)])
+def test_q_factor_orthonormal_and_reconstructs(m, n, seed):
+    A = inputs.uniform(m, n, seed)
+    Q = oracle.q_factor(A)
+    R = oracle.r_factor(A)
+    assert Q.shape == (m, n)
+    assert np.linalg.norm(Q.T @ Q - np.eye(n)) < 1e-13 * max(1.0, np.linalg.cond(A))
+    assert np.linalg.norm(Q @ R - A) / np.linalg.norm(A) < 1e-14
+
+
+def test_q_factor_single_column_closed_form():
+    a = inputs.uniform(777, 1, 8)
+    q = oracle.q_factor(a)
+    np.testing.assert_allclose(q[:, 0], a[:, 0] / np.linalg.norm(a[:, 0]), rtol=0, atol=1e-16)
+
+
+def test_q_factor_matches_lapack_up_to_column_signs():
+    A = inputs.uniform(2000, 20, 9)
+    Qn, Rn = np.linalg.qr(A)
+    Q = oracle.q_factor(A)
+    assert np.abs(Q - Qn * np.sign(np.diag(Rn))).max() < 1e-14
+
+
+def test_q_factor_exact_for_hadamard_construction():
+    # A = H R_true with H orthonormal (scaled Hadamard columns) exactly: Q = H
+    A, Rt = inputs.hadamard_exact(4096, 16, seed=2)
+    H = np.linalg.solve(Rt.T, A.T).T            # exact up to rounding: the scaled Hadamard columns
+    Q = oracle.q_factor(A)
+    assert np.abs(Q - H).max() < 1e-15 * 64
+    assert set(np.unique(np.round(np.abs(H) * 64, 9))) == {1.0}
+
+
+def test_q_factor_diagonal_input_is_identity_bitexact():
+    d = np.array([3.0, 0.5, 7.25, 1e-3])
+    Q = oracle.q_factor(np.diag(d))
+    assert np.array_equal(Q, np.eye(4))
+
+
+def test_q_factor_refuses_rank_deficient_and_wide_inputs():
+    A = inputs.uniform(50, 4, 10)
+    A[:, 2] = 0.0
+    with pytest.raises(RuntimeError):
+        oracle.q_factor(A)
+    with pytest.raises(RuntimeError):
+        oracle.q_factor(inputs.uniform(3, 5, 11))
