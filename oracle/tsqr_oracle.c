@@ -3,7 +3,7 @@
  *
  * TEST INFRASTRUCTURE ONLY.  Plain, slow, single-threaded IEEE double code
  * that the tests, the package smoke check and the benchmark's CPU-baseline leg
- * use to judge the GPU library.  It shares no code, header, table or helper
+ * use to check the GPU library.  It shares no code, header, table or helper
  * with the GPU path and must never be linked into it or called by it.
  *
  * Source: J. Langou, "Computing the R of the QR factorization of tall and
