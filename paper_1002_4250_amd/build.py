@@ -65,7 +65,9 @@ def _digest(names):
             h.update(name.encode() + f.read())
     with open(os.path.join(INCLUDE, "tsqr.h"), "rb") as f:
         h.update(f.read())
-    h.update(" ".join(COMMON).encode())
+    # the compiler flags, without the include paths: the digest must not depend
+    # on where the repository sits
+    h.update(" ".join(f for f in COMMON if not f.startswith("-I")).encode())
     return h.hexdigest()[:16]
 
 
