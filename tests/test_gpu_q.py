@@ -145,3 +145,57 @@ def test_q_fp32_argument_errors():
     with pytest.raises(TypeError):
         tsqr.geqr_qr(torch.zeros((10, 2), dtype=torch.float16, device="cuda"))
 
+
+
+def test_q_in_hip_graph_matches_eager():
+    """The Q-factor call is a fixed sequence of kernel launches with no memset
+    and no allocation (workspace and outputs given), so it can be captured;
+    every replay, with eager work between replays, equals the eager result."""
+    m, n = 70000, 50
+    A = inputs.uniform(m, n, 21)
+    Ad = to_dev(A)
+    h = tsqr.handle(0)
+    ws = torch.empty(tsqr.tsqr_qr_workspace_bytes(h, m, n), dtype=torch.uint8, device="cuda")
+    Q = torch.empty((n, m), dtype=torch.float64, device="cuda").t()
+    R = torch.empty((n, n), dtype=torch.float64, device="cuda").t()
+    tsqr.geqr_qr(Ad, Q=Q, R=R, ws=ws, h=h)
+    torch.cuda.synchronize()
+    Qe, Re = Q.clone(), R.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        tsqr.geqr_qr(Ad, Q=Q, R=R, ws=ws, h=h)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        tsqr.geqr_qr(Ad, Q=Q, R=R, ws=ws, h=h)
+    for i in range(3):
+        Q.fill_(float("nan"))
+        R.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Q, Qe) and torch.equal(R, Re), i
+        tsqr.geqr_r(Ad, h=h)                      # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_binding_refuses_mis_shaped_device_outputs():
+    """Outputs of the wrong shape, type or layout are refused before any launch."""
+    A = to_dev(inputs.uniform(300, 7, 22))
+    with pytest.raises(ValueError):
+        tsqr.geqr_r(A, R=torch.empty((6, 6), dtype=torch.float64, device="cuda").t())
+    with pytest.raises(TypeError):
+        tsqr.geqr_r(A, R=torch.empty((7, 7), dtype=torch.float32, device="cuda").t())
+    with pytest.raises(ValueError):
+        tsqr.geqr_r(A, R=torch.empty((7, 7), dtype=torch.float64, device="cuda"))     # row-major
+    with pytest.raises(ValueError):
+        tsqr.geqr_qr(A, Q=torch.empty((7, 299), dtype=torch.float64, device="cuda").t())
+    flat = torch.zeros(1000 * 7, dtype=torch.float32, device="cuda")
+    plan = tsqr.BatchPlan([1000], [0], 7, torch.float32)
+    with pytest.raises(ValueError):
+        plan.run(flat, torch.empty((1, 7, 6), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        plan.run(flat[:6999])
+    torch.cuda.synchronize()
