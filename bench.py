@@ -139,8 +139,18 @@ def time_q(torch, tsqr, Ad, steps, warmup, library=True):
             lib_r_ms = timed(lambda: torch.linalg.qr(Ad, mode="r"), 3, 1)
         except RuntimeError as e:      # the library path is context only
             log(f"q: torch.linalg.qr unavailable: {e}")
+    # the same call in FP32 (input: the FP32 rounding of A)
+    A32 = Ad.float().t().contiguous().t()
+    ws32 = torch.empty(tsqr.tsqr_qr_workspace_bytes(h, m, n, tsqr.TSQR_F32), dtype=torch.uint8, device="cuda")
+    Q32 = torch.empty((n, m), dtype=torch.float32, device="cuda").t()
+    R32 = torch.empty((n, n), dtype=torch.float32, device="cuda").t()
+    ms_q32 = timed(lambda: tsqr.geqr_qr(A32, Q=Q32, R=R32, ws=ws32, h=h), k, min(warmup, 10))
+    orth32 = float(torch.linalg.norm(Q32.double().t() @ Q32.double()
+                                     - torch.eye(n, dtype=torch.float64, device="cuda")).item()) / n ** 0.5
+    del A32, ws32, Q32, R32
     flops = 4.0 * m * n * n        # factorization 2mn^2 + forming Q 2mn^2 (LAPACK's counts for m >> n)
     gbs_min = 16.0 * m * n / (ms_q * 1e-3) / 1e9
+    log(f"q: fp32 {ms_q32:.3f} ms per QR with Q, orthogonality {orth32:.1e}")
     log(f"q: {ms_q:.3f} ms per QR with Q ({flops / (ms_q * 1e-3) / 1e12:.2f} TFLOP/s at 4mn^2); "
         f"orth {orth:.1e} resid {resid:.1e}; torch.linalg.qr {lib_ms} ms (mode r {lib_r_ms} ms)")
     return {
@@ -151,6 +161,8 @@ def time_q(torch, tsqr, Ad, steps, warmup, library=True):
         "min_hbm_GBs_read_A_write_Q": gbs_min,
         "orthogonality": orth, "residual": resid,
         "torch_linalg_qr_reduced_ms": lib_ms, "torch_linalg_qr_r_ms": lib_r_ms,
+        "fp32": {"value": 1000.0 / ms_q32, "unit": "instances/s", "ms_per_step": ms_q32,
+                 "achieved_TFLOPs_4mn2": flops / (ms_q32 * 1e-3) / 1e12, "orthogonality": orth32},
     }
 
 
