@@ -75,3 +75,19 @@ def test_tuned_batch_matches_oracle(tuned):
         s = np.linalg.svd(A, compute_uv=False)
         tol = 1e-5 * max(1.0, float(s[0] / s[-1]) / 10.0)
         assert relF(Rb[b].T, oracle.r_factor(A)) < tol, b
+
+
+def test_tuner_runs_end_to_end():
+    """A small tuning run (one bucket, one element type, a small batch)
+    produces a table whose entries are the fastest of their candidates and
+    that a fresh handle accepts."""
+    table = autotune.tune(n=16, dtypes=("f32",), buckets=[4096], batch_count=64, reps=2)
+    ents = table["entries"]
+    assert [e["batch"] for e in ents] == [False, True]
+    for e in ents:
+        assert e["us"] == min(c[2] for c in e["candidates"]) > 0
+    h = tsqr.tsqr_create(0)
+    try:
+        assert autotune.apply(h, table) == 2
+    finally:
+        tsqr.tsqr_destroy(h)
