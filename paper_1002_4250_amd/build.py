@@ -18,7 +18,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-CSRC = os.environ.get("TSQR_CSRC", os.path.join(PKG, "csrc"))
+CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libtsqr.so")
@@ -28,10 +28,6 @@ ARCH = "gfx950"
 # packed FP32 instructions are kept out of every kernel
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["--offload-arch=" + ARCH, "-O3", "-std=c++20", "-fPIC", "-I" + INCLUDE, "-I" + CSRC] + DEVICE_FLAGS
-# experiment hooks: extra compiler flags and an alternative output library
-COMMON += os.environ.get("TSQR_EXTRA_FLAGS", "").split()
-LIB = os.environ.get("TSQR_LIB_OUT", LIB)
-BUILD = os.environ.get("TSQR_BUILD_DIR", BUILD)
 
 
 def instances():

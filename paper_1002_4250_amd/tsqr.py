@@ -200,7 +200,11 @@ def _col_major(A):
     s0, s1 = A.stride()
     if s0 != 1 and m > 1:
         raise ValueError("A must be column-major: A.stride(0) == 1 (use A.t().contiguous().t())")
-    lda = max(s1, max(m, 1)) if n > 1 else max(m, 1)
+    if n > 1 and s1 < max(m, 1):
+        # an expanded or overlapping view: the kernels read m*n distinct elements
+        raise ValueError("A has a column stride below its row count (expanded or overlapping view); "
+                         "pass A.contiguous() in column-major order")
+    lda = s1 if n > 1 else max(m, 1)
     return m, n, lda
 
 

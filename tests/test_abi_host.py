@@ -364,6 +364,17 @@ def test_binding_refuses_wrong_tensors():
     col = torch.empty((3, 8), dtype=torch.float64)[:, 0:1]           # a strided column
     with pytest.raises(ValueError):
         tsqr._check_matrix(col, "Q", 3, 1, torch.float64, cpu)
+    # input matrices: an expanded or overlapping view has a column stride below
+    # m, and the kernels would read m*n elements from a smaller allocation
+    assert tsqr._col_major(torch.empty((50, 1000), dtype=torch.float64).t()) == (1000, 50, 1000)
+    assert tsqr._col_major(torch.empty((50, 1200), dtype=torch.float64).t()[:1000, :]) == (1000, 50, 1200)
+    with pytest.raises(ValueError):
+        tsqr._col_major(torch.zeros(1000, 1, dtype=torch.float64).expand(1000, 50))
+    with pytest.raises(ValueError):
+        tsqr._col_major(torch.zeros(2000, dtype=torch.float64).as_strided((1000, 50), (1, 10)))
+    with pytest.raises(ValueError):
+        tsqr._col_major(torch.empty((1000, 50), dtype=torch.float64))          # row-major
+    assert tsqr._col_major(torch.zeros(1000, 1, dtype=torch.float64)) == (1000, 1, 1000)
     flat = torch.empty(100, dtype=torch.float32)
     tsqr._check_flat(flat, "A", 100, torch.float32, cpu)
     with pytest.raises(ValueError):
