@@ -19,6 +19,12 @@ unless stated):
 * :func:`normalize_signs` -- the positive-diagonal convention (section 2).
 * :func:`q_factor` -- the Q that goes with that R for A of full column rank,
   by its definition Q = A R^-1 (the Q section 3 leaves implicit); m-by-n.
+* :func:`gram` -- A^T A with every entry summed in double-double.
+* :func:`gram_residual` -- the backward error ||R^T R - A^T A||_F / ||A||_F^2
+  of a computed R, formed in double-double (every R of section 2 satisfies
+  R^T R = A^T A in exact arithmetic).
+* :mod:`oracle.parallel` -- the same functions over many instances in a pool
+  of host processes.
 """
 from __future__ import annotations
 
@@ -68,6 +74,9 @@ def _lib():
             lib.oracle_normalize_signs.restype = None
             lib.oracle_tsqr_flops.argtypes = [_i64, _i64, _i64]
             lib.oracle_tsqr_flops.restype = ctypes.c_double
+            lib.oracle_gram.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64]
+            lib.oracle_gram_residual.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64]
+            lib.oracle_gram_residual.restype = ctypes.c_double
             _LIB = lib
         return _LIB
 
@@ -167,3 +176,33 @@ def normalize_signs(R) -> np.ndarray:
 def tsqr_flops(m: int, n: int, leaf_rows: int) -> float:
     """Flop count of :func:`tsqr_r` in the paper's cost model."""
     return float(_lib().oracle_tsqr_flops(m, n, leaf_rows))
+
+
+def gram(A) -> np.ndarray:
+    """A^T A (n-by-n), every entry summed in double-double from exact
+    products and rounded once."""
+    A = _fortran64(A)
+    m, n = A.shape
+    G = np.zeros((n, n), dtype=np.float64, order="F")
+    if n == 0:
+        return G
+    _check(_lib().oracle_gram(m, n, _ptr(A), max(1, m), _ptr(G), max(1, n)), "oracle_gram")
+    return G
+
+
+def gram_residual(A, R) -> float:
+    """||R^T R - A^T A||_F / ||A||_F^2 for the m-by-n A and the n-by-n upper
+    triangle of R (its strict lower part is ignored), formed in double-double:
+    the backward error of R as a QR factor of A.  Independent of the condition
+    number of A, unlike the forward error of R."""
+    A = _fortran64(A)
+    R = _fortran64(R)
+    m, n = A.shape
+    if R.shape != (n, n):
+        raise ValueError("R must be n-by-n")
+    if n == 0 or m == 0:
+        return 0.0
+    v = float(_lib().oracle_gram_residual(m, n, _ptr(A), max(1, m), _ptr(R), max(1, n)))
+    if v < 0:
+        raise ValueError("gram_residual: A is zero or sizes are invalid")
+    return v

@@ -37,6 +37,14 @@
  *                             is the unique m-by-n matrix with orthonormal
  *                             columns and A = QR, diag(R) > 0 (the Q that
  *                             section 3 notes a reduction leaves implicit).
+ *   oracle_gram            -- the Gram matrix A^T A, each entry summed in
+ *                             double-double arithmetic from exact products
+ *                             (the identity R^T R = A^T A that every R of
+ *                             section 2 satisfies, whatever the tree).
+ *   oracle_gram_residual   -- ||R^T R - A^T A||_F / ||A||_F^2 with both Gram
+ *                             matrices and their difference carried in
+ *                             double-double: the backward error of a
+ *                             computed R, accurate far below FP64 rounding.
  *
  * Storage is column-major throughout: element (i, j) of a matrix with leading
  * dimension ld sits at index i + j*ld.  Return value 0 means success; a
@@ -392,4 +400,132 @@ double oracle_tsqr_flops(int64_t m, int64_t n, int64_t leaf_rows)
     for (int64_t p = 1; p < P; ++p)
         for (int64_t j = 0; j < n; ++j) total += 4.0 * (double)(j + 1) * (double)(n - 1 - j);
     return total;
+}
+
+/* ---- Gram matrices in double-double ---------------------------------------
+ *
+ * A double-double value is an unevaluated sum hi + lo with |lo| <= ulp(hi)/2.
+ * two_sum and two_prod are the error-free transformations of Knuth and
+ * Dekker (the product's rounding error is exact through fma), so a dot product
+ * accumulated this way carries an error of order 2^-104 relative to the sum
+ * of |terms|, independent of the number of terms. */
+typedef struct { double hi, lo; } dd_t;
+
+static void two_sum(double a, double b, double *s, double *e)
+{
+    double x = a + b;
+    double bv = x - a;
+    double av = x - bv;
+    *s = x;
+    *e = (a - av) + (b - bv);
+}
+
+static void dd_add_prod(dd_t *acc, double a, double b)
+{
+    double p = a * b;
+    double pe = fma(a, b, -p);       /* a*b = p + pe exactly */
+    double s, e;
+    two_sum(acc->hi, p, &s, &e);
+    e += acc->lo + pe;
+    two_sum(s, e, &acc->hi, &acc->lo);
+}
+
+static dd_t dd_sub(dd_t a, dd_t b)
+{
+    double s, e;
+    two_sum(a.hi, -b.hi, &s, &e);
+    e += a.lo - b.lo;
+    dd_t r;
+    two_sum(s, e, &r.hi, &r.lo);
+    return r;
+}
+
+/* The upper triangle (j <= k) of X^T X for an m-by-n X in double-double,
+ * packed by rows of the triangle into acc[0 .. n(n+1)/2).  Rows of X are taken
+ * one at a time (through a small row buffer), so every accumulator of the row
+ * is independent of the others and the loop pipelines. */
+static int gram_dd(int64_t m, int64_t n, const double *X, int64_t ldx, dd_t *acc)
+{
+    double *row = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    if (!row) return -1;
+    int64_t nt = n * (n + 1) / 2;
+    for (int64_t t = 0; t < nt; ++t) acc[t].hi = acc[t].lo = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        for (int64_t j = 0; j < n; ++j) row[j] = X[IDX(i, j, ldx)];
+        dd_t *a = acc;
+        for (int64_t j = 0; j < n; ++j) {
+            double xj = row[j];
+            for (int64_t k = j; k < n; ++k) dd_add_prod(a++, xj, row[k]);
+        }
+    }
+    free(row);
+    return 0;
+}
+
+/* G = A^T A (n-by-n, leading dimension ldg), each entry rounded once from its
+ * double-double sum. */
+int oracle_gram(int64_t m, int64_t n, const double *A, int64_t lda, double *G, int64_t ldg)
+{
+    if (m < 0) return -1;
+    if (n < 0) return -2;
+    if (lda < (m > 1 ? m : 1)) return -4;
+    if (ldg < (n > 1 ? n : 1)) return -6;
+    dd_t *acc = (dd_t *)malloc((size_t)(n * (n + 1) / 2 + 1) * sizeof(dd_t));
+    if (!acc) return -7;
+    if (gram_dd(m, n, A, lda, acc) != 0) {
+        free(acc);
+        return -7;
+    }
+    const dd_t *a = acc;
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t k = j; k < n; ++k, ++a) G[IDX(j, k, ldg)] = G[IDX(k, j, ldg)] = a->hi + a->lo;
+    free(acc);
+    return 0;
+}
+
+/* ||R^T R - A^T A||_F / ||A||_F^2 for an m-by-n A and an n-by-n R (only its
+ * upper triangle is read).  Both Gram matrices and each difference are formed
+ * in double-double; the norms are summed from the rounded differences.
+ * Returns -1 if A is zero (result undefined), -2 for bad sizes or no memory,
+ * else the ratio. */
+double oracle_gram_residual(int64_t m, int64_t n, const double *A, int64_t lda, const double *R, int64_t ldr)
+{
+    if (m < 0 || n < 0 || lda < (m > 1 ? m : 1) || ldr < (n > 1 ? n : 1)) return -2.0;
+    int64_t nt = n * (n + 1) / 2;
+    dd_t *ga = (dd_t *)malloc((size_t)(nt + 1) * sizeof(dd_t));
+    dd_t *gr = (dd_t *)malloc((size_t)(nt + 1) * sizeof(dd_t));
+    double *Ru = (double *)calloc((size_t)(n * n + 1), sizeof(double));
+    if (!ga || !gr || !Ru || gram_dd(m, n, A, lda, ga) != 0) {
+        free(ga);
+        free(gr);
+        free(Ru);
+        return -2.0;
+    }
+    /* the upper triangle of R, zeros below */
+    for (int64_t k = 0; k < n; ++k)
+        for (int64_t i = 0; i <= k; ++i) Ru[IDX(i, k, n)] = R[IDX(i, k, ldr)];
+    if (gram_dd(n, n, Ru, n, gr) != 0) {
+        free(ga);
+        free(gr);
+        free(Ru);
+        return -2.0;
+    }
+    csum_t num = {0.0, 0.0}, den = {0.0, 0.0};
+    int64_t t = 0;
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t k = j; k < n; ++k, ++t) {
+            dd_t d = dd_sub(gr[t], ga[t]);
+            double v = d.hi + d.lo;
+            csum_add(&num, (j == k ? 1.0 : 2.0) * v * v);    /* off-diagonal entries appear twice */
+            if (j == k) {
+                csum_add(&den, ga[t].hi);
+                csum_add(&den, ga[t].lo);
+            }
+        }
+    free(ga);
+    free(gr);
+    free(Ru);
+    double dn = csum_value(&den);
+    if (!(dn > 0.0)) return -1.0;
+    return sqrt(csum_value(&num)) / dn;
 }

@@ -2,17 +2,21 @@
 against the CPU oracle, through the C ABI.
 
 The oracle is the definition (FP64 Householder QR) run on the FP32-stored
-input promoted to FP64.  Both sides then carry FP64 rounding amplified by the
-condition number, so the gate is relF <= 1e-13 * max(1, kappa): at kappa = 1
-that is 1e-13 (plain FP64 results agree to about 1e-15), and it grows with
-kappa as the forward error of R does.  Instances whose Gram matrix is not
+input promoted to FP64.  Every instance must meet three gates (tests/gates.py):
+the global forward error relF <= 1e-13 * max(1, kappa); the backward error
+||R^T R - A^T A||_F / ||A||_F^2 <= 1e-14, independent of kappa; and the
+row-scaled forward error <= 1e-14 * max(1, kappa)^0.6, which sees the small
+trailing rows.  The last two are what an FP32-accurate R cannot meet: a
+control checks that the uncorrected FP32 factor fails them from kappa = 1e6
+up (it passes the relF gate there).  Instances whose Gram matrix is not
 numerically positive definite must be reported as refactored in FP64 and meet
-the same gate.
+the same gates.
 """
 import numpy as np
 import pytest
 
 import oracle
+from gates import GRAM64, kappa_of, row_gate64, row_scaled
 from paper_1002_4250_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -46,6 +50,9 @@ def test_mixed_matches_oracle_over_kappa(m, n):
         Rg = Rb[b].T
         tol = 1e-13 * max(1.0, kappas[b])
         assert relF(Rg, Ro) < tol, (b, kappas[b], fb[b], relF(Rg, Ro))
+        assert oracle.gram_residual(A, Rg) < GRAM64, (b, kappas[b], oracle.gram_residual(A, Rg))
+        k = kappa_of(Ro)
+        assert row_scaled(Rg, Ro) < row_gate64(k), (b, k, row_scaled(Rg, Ro))
         assert np.all(np.tril(Rg, -1) == 0) and np.all(np.diag(Rg) > 0), b
     # well-conditioned instances take the corrected FP32 path
     assert all(fb[b] == 0 for b in range(batch) if kappas[b] <= 1e4), fb
@@ -84,6 +91,27 @@ def test_mixed_is_more_accurate_than_fp32():
     R32 = tsqr.geqr_r(torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t()).cpu().numpy().astype(np.float64)
     e_mixed, e_32 = relF(Rb[0].T, Ro), relF(R32, Ro)
     assert e_mixed < 1e-12 and e_32 > 1e-9, (e_mixed, e_32)
+
+
+@pytest.mark.parametrize("kappa", [1e6, 1e7, 1e8])
+def test_gates_reject_the_uncorrected_fp32_factor(kappa):
+    """Control: the FP32 TSQR factor alone fails the backward-error and
+    row-scaled gates, which the corrected result meets; from kappa = 1e7 up it
+    passes the global relF gate (its error is dominated by the leading rows),
+    which is why that gate alone cannot tell the two apart."""
+    m, n = 16384, 50
+    A = inputs.conditioned(m, n, kappa, seed=31)
+    Rb, fb, _ = run_mixed(A.T.ravel().copy(), 1, m, n)
+    A64 = np.asfortranarray(A.astype(np.float64))
+    Ro = oracle.r_factor(A64)
+    k = kappa_of(Ro)
+    R32 = tsqr.geqr_r(torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t()).cpu().numpy().astype(np.float64)
+    if kappa >= 1e7:
+        assert relF(R32, Ro) < 1e-13 * max(1.0, kappa)             # relF alone is blind here
+    assert oracle.gram_residual(A64, R32) > GRAM64 * 100, oracle.gram_residual(A64, R32)
+    assert row_scaled(R32, Ro) > row_gate64(k) * 10, (row_scaled(R32, Ro), row_gate64(k))
+    Rg = Rb[0].T
+    assert oracle.gram_residual(A64, Rg) < GRAM64 and row_scaled(Rg, Ro) < row_gate64(k), fb
 
 
 def test_mixed_bitwise_reproducible_and_strided():

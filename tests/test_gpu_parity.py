@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
+from gates import GRAM32, GRAM64, kappa_of, row_gate64, row_scaled
 from paper_1002_4250_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -127,7 +128,11 @@ def test_config1_small_instance():
                                  (777, 32), (3000, 49)])
 def test_ragged_sizes(m, n):
     A = inputs.uniform(m, n, 1000 + m + n)
-    assert relF(gpu_r(A), oracle.r_factor(A)) < TOL64
+    R, Ro = gpu_r(A), oracle.r_factor(A)
+    assert relF(R, Ro) < TOL64
+    assert oracle.gram_residual(A, R) < GRAM64
+    if m >= n:
+        assert row_scaled(R, Ro) < row_gate64(kappa_of(Ro))
 
 
 @pytest.mark.parametrize("leaf_rows", [64, 128, 256, 1024, 5000, 20000])
@@ -239,6 +244,7 @@ def test_fp32_matches_oracle_on_rounded_input(m, n):
     R = gpu_r(A32)
     assert R.dtype == np.float32
     assert relF(R.astype(np.float64), oracle.r_factor(A32.astype(np.float64))) < TOL32
+    assert oracle.gram_residual(A32.astype(np.float64), R.astype(np.float64)) < GRAM32
     assert not np.signbit(np.diag(R)).any() and not np.tril(R, -1).any()
 
 
@@ -253,6 +259,8 @@ def test_full_size_fp64_uniform_vs_oracle():
     Ro = oracle.r_factor(A)
     assert relF(R, Ro) < TOL64
     assert np.abs(R - Ro).max() / np.abs(Ro).max() < TOL64
+    assert row_scaled(R, Ro) < row_gate64(kappa_of(Ro))
+    assert oracle.gram_residual(A, R) < GRAM64
 
 
 def test_full_size_fp64_hadamard_exact():
@@ -267,6 +275,7 @@ def test_full_size_fp32_uniform_vs_oracle():
     R = gpu_r(A32)
     Ro = oracle.r_factor(A32.astype(np.float64))
     assert relF(R.astype(np.float64), Ro) < TOL32
+    assert oracle.gram_residual(A32.astype(np.float64), R.astype(np.float64)) < GRAM32
 
 
 def test_plain_call_in_hip_graph_matches_eager():

@@ -387,3 +387,98 @@ def test_q_factor_refuses_rank_deficient_and_wide_inputs():
         oracle.q_factor(A)
     with pytest.raises(RuntimeError):
         oracle.q_factor(inputs.uniform(3, 5, 11))
+
+
+# ---- the Gram matrix and the backward error (used as kappa-free parity gates) ----
+
+def _exact_gram(A):
+    """A^T A in exact rational arithmetic (fractions), rounded to doubles."""
+    from fractions import Fraction
+    F = [[Fraction(float(v)) for v in col] for col in np.asarray(A, dtype=np.float64).T]
+    n = len(F)
+    return np.array([[float(sum(a * b for a, b in zip(F[j], F[k]))) for k in range(n)] for j in range(n)])
+
+
+def test_gram_integer_matrices_exact():
+    rng = np.random.default_rng(21)
+    A = rng.integers(-1000, 1000, size=(300, 7)).astype(np.float64)
+    Ai = A.astype(np.int64)
+    assert np.array_equal(oracle.gram(A), (Ai.T @ Ai).astype(np.float64))
+
+
+def test_gram_wide_dynamic_range_is_correctly_rounded():
+    """Entries spanning 2^-60 .. 2^60: the double-double sum rounds to the
+    exactly rounded value of the rational sum (a plain double sum does not)."""
+    rng = np.random.default_rng(22)
+    A = np.ldexp(rng.uniform(-1, 1, size=(60, 4)), rng.integers(-60, 61, size=(60, 4)))
+    G = oracle.gram(A)
+    Ge = _exact_gram(A)
+    assert np.array_equal(G, Ge)
+    assert np.array_equal(G, G.T)
+
+
+def test_gram_residual_zero_for_exact_construction():
+    """A = Q R_true exactly with Q's columns exactly orthonormal: R_true^T
+    R_true = A^T A holds exactly, and the double-double residual is exactly 0."""
+    for grade in (0, 26):
+        A, Rt = inputs.hadamard_exact(1024, 12, seed=23, grade_bits=grade)
+        assert oracle.gram_residual(A, Rt) == 0.0
+        # the strict lower triangle of R is ignored
+        Rl = Rt.copy()
+        Rl[5, 2] = 7.0
+        assert oracle.gram_residual(A, Rl) == 0.0
+
+
+def test_gram_residual_closed_form_for_one_perturbed_entry():
+    """R = R_true + d e_i e_k^T changes R^T R by d (e_k r_i^T + r_i e_k^T) +
+    d^2 e_k e_k^T (r_i = row i of R_true): the residual equals the norm of that
+    matrix over ||A||_F^2, computed here exactly with fractions."""
+    from fractions import Fraction
+    A, Rt = inputs.hadamard_exact(256, 9, seed=24)
+    nA2 = sum(Fraction(float(v)) ** 2 for v in A.ravel())
+    for (i, k, d) in [(0, 0, 2.0 ** -20), (3, 7, -1e-9), (8, 8, 0.5)]:
+        R = Rt.copy()
+        R[i, k] += d
+        d = Fraction(float(R[i, k])) - Fraction(float(Rt[i, k]))   # the perturbation as stored
+        ri = [Fraction(float(v)) for v in Rt[i]]
+        D = [[Fraction(0)] * 9 for _ in range(9)]
+        for c in range(9):
+            D[k][c] += d * ri[c]
+            D[c][k] += d * ri[c]
+        D[k][k] += d * d
+        expect = math.sqrt(float(sum(x * x for row in D for x in row))) / float(nA2)
+        got = oracle.gram_residual(A, R)
+        assert abs(got - expect) <= 1e-12 * expect, (i, k, d, got, expect)
+
+
+def test_gram_residual_is_kappa_free_and_catches_fp32():
+    """The residual of an FP64 Householder R stays at the FP64 rounding level
+    whatever the condition number, while an R computed in FP32 (LAPACK
+    sgeqrf) sits near the FP32 rounding level: the property that makes it a
+    parity gate able to reject an uncorrected FP32 factor."""
+    for kappa in (1.0, 1e4, 1e8):
+        A = inputs.conditioned(4096, 30, kappa, seed=25)
+        A64 = A.astype(np.float64)
+        r64 = oracle.gram_residual(A64, oracle.r_factor(A64))
+        r32 = oracle.gram_residual(A64, np.linalg.qr(A, mode="r").astype(np.float64))
+        assert r64 < 1e-15 and r32 > 1e-11, (kappa, r64, r32)
+
+
+def test_parallel_check_batch_equals_serial_oracle():
+    """oracle.parallel gives, bit for bit, the serial oracle's R and backward
+    error for every instance of a ragged batch (including empty ones)."""
+    from oracle import parallel
+    n = 9
+    sizes = [0, 1, 5, 9, 300, 2000]
+    offsets = np.concatenate([[0], np.cumsum(np.array(sizes[:-1]) * n)])
+    rng = np.random.default_rng(26)
+    flat = rng.uniform(-1, 1, int(sum(sizes)) * n).astype(np.float32)
+    Rt = [np.triu(rng.uniform(-1, 1, (n, n))) for _ in sizes]
+    Ro, g = parallel.check_batch(flat, [(o, m, n, m) for o, m in zip(offsets, sizes)], Rt, nproc=2)
+    for b, (o, m) in enumerate(zip(offsets, sizes)):
+        A = flat[o:o + m * n].reshape(n, m).T.astype(np.float64)
+        if m == 0:
+            assert np.all(Ro[b] == 0) and g[b] == 0.0
+            continue
+        assert np.array_equal(Ro[b], oracle.r_factor(A)), b
+        assert g[b] == oracle.gram_residual(A, Rt[b]), b
