@@ -57,6 +57,7 @@ extern "C" {
 #define TSQR_ERR_UNSUPPORTED 2  /* n > TSQR_MAX_N, or a size beyond the kernels' index range */
 #define TSQR_ERR_NO_DEVICE 3    /* no usable gfx950 device */
 #define TSQR_ERR_ALLOC 4        /* host or device allocation failed (plan creation only) */
+#define TSQR_ERR_SCRATCH 5      /* tsqr_geqr_r_f64_noalloc: the problem needs more than its fixed scratch */
 
 /* options for tsqr_set_option (0 restores the automatic choice) */
 #define TSQR_OPT_LEAF_ROWS 1      /* rows per leaf block; rounded up to a whole chunk */
@@ -155,6 +156,27 @@ int tsqr_geqr_r_f64(tsqr_handle_t handle, int64_t m, int64_t n, const double *A,
                     double *R, int64_t ldr, void *ws, int64_t ws_bytes, void *stream);
 int tsqr_geqr_r_f32(tsqr_handle_t handle, int64_t m, int64_t n, const float *A, int64_t lda,
                     float *R, int64_t ldr, void *ws, int64_t ws_bytes, void *stream);
+
+/* For callers that cannot allocate device memory or pass a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): tsqr_geqr_r_f64 with the workspace taken from a fixed array that
+ * the library holds on every device it runs on (TSQR_NOALLOC_SCRATCH_BYTES per
+ * device, kept until the process ends; its address is looked up once per
+ * device when a handle is created).  Same arguments as tsqr_geqr_r_f64 minus
+ * the workspace; same kernels, launch geometry and result, bit for bit.  The
+ * call allocates nothing: it launches the counter-clearing kernel and the
+ * factorization on `stream`.  All calls on one device share the array, so
+ * calls that may overlap on one device (other streams, other threads, other
+ * handles) race and must be serialized by the caller.  Returns
+ * TSQR_ERR_SCRATCH, before any launch, if the workspace the plan needs (see
+ * tsqr_workspace_bytes) exceeds TSQR_NOALLOC_SCRATCH_BYTES: with the
+ * built-in leaf policy on an MI355X (at most 1024 leaves in FP64, 17 MB at
+ * n = 64) every n <= TSQR_MAX_N and any m fit; a small TSQR_OPT_LEAF_ROWS or
+ * a large TSQR_OPT_WAVES_PER_CU on a large m can exceed it.  Argument codes: -1
+ * handle, -2 m, -3 n, -4 A, -5 lda, -6 R, -7 ldr. */
+#define TSQR_NOALLOC_SCRATCH_BYTES ((int64_t)32 << 20)
+int tsqr_geqr_r_f64_noalloc(tsqr_handle_t handle, int64_t m, int64_t n, const double *A, int64_t lda,
+                            double *R, int64_t ldr, void *stream);
 
 /* The paper's reduction operator (section 3, Table 3: LILA_qr_uppers) on two
  * n-by-n upper triangles stacked as [R1; R2], same contract:

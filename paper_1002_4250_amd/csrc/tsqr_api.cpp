@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string.h>
 #include <vector>
@@ -26,6 +27,7 @@ struct TuneEntry {
 
 struct tsqr_handle_s {
     int device;
+    void* scratch;         // this device's address of the fixed scratch array (tsqr_geqr_r_f64_noalloc)
     int cu_count;
     int64_t leaf_rows;     // 0 = automatic
     int64_t rpl;           // rows per lane of the leaf kernel; 0 = default
@@ -35,7 +37,30 @@ struct tsqr_handle_s {
     std::vector<TuneEntry> tuning;
 };
 
+// Fixed scratch for tsqr_geqr_r_f64_noalloc: the tree counters and leaf
+// triangles that tsqr_geqr_r_f64 takes from the caller's workspace.  Every
+// device the library runs on holds its own copy until the process ends.  In
+// host code `scratch` is only a stand-in for the symbol: its device address
+// comes from hipGetSymbolAddress, once per device (device_scratch).
+static __device__ __align__(256) unsigned char scratch[TSQR_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+// Device address of `scratch` on `device` (which must be current), looked up
+// once per device; nullptr if the lookup fails.
+void* device_scratch(int device)
+{
+    static std::mutex mu;
+    static std::vector<void*> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (device < 0) return nullptr;
+    if ((int)addr.size() <= device) addr.resize(device + 1, nullptr);
+    if (!addr[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) addr[device] = p;
+    }
+    return addr[device];
+}
 
 constexpr int kRowsPerLaneUnit = 16;   // a chunk is 16 * rows-per-lane rows (16 lanes share a column)
 constexpr int64_t kAlign = 256;
@@ -275,6 +300,7 @@ int tsqr_create(tsqr_handle_t* handle, int device)
     tsqr_handle_s* h = new (std::nothrow) tsqr_handle_s;
     if (!h) return TSQR_ERR_ALLOC;
     h->device = device;
+    h->scratch = device_scratch(device);
     h->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     h->leaf_rows = 0;
     h->rpl = 0;
@@ -293,6 +319,7 @@ int tsqr_create_planning(tsqr_handle_t* handle, int cu_count)
     tsqr_handle_s* h = new (std::nothrow) tsqr_handle_s;
     if (!h) return TSQR_ERR_ALLOC;
     h->device = -1;
+    h->scratch = nullptr;
     h->cu_count = cu_count;
     h->leaf_rows = 0;
     h->rpl = 0;
@@ -320,6 +347,7 @@ const char* tsqr_status_string(int status)
     case TSQR_ERR_UNSUPPORTED: return "unsupported size (n > TSQR_MAX_N or index range)";
     case TSQR_ERR_NO_DEVICE: return "no usable gfx950 device";
     case TSQR_ERR_ALLOC: return "allocation failed";
+    case TSQR_ERR_SCRATCH: return "problem needs more than the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
     }
 }
@@ -426,6 +454,30 @@ int tsqr_geqr_r_f64(tsqr_handle_t handle, int64_t m, int64_t n, const double* A,
                     int64_t ldr, void* ws, int64_t ws_bytes, void* stream)
 {
     return geqr_r<double>(handle, m, n, A, lda, R, ldr, ws, ws_bytes, stream, TSQR_F64);
+}
+
+int tsqr_geqr_r_f64_noalloc(tsqr_handle_t handle, int64_t m, int64_t n, const double* A, int64_t lda, double* R,
+                            int64_t ldr, void* stream)
+{
+    if (!handle) return -1;
+    if (m < 0) return -2;
+    if (n < 0) return -3;
+    if (m > 0 && n > 0 && !A) return -4;
+    if (lda < (m > 1 ? m : 1)) return -5;
+    if (n > 0 && !R) return -6;
+    if (ldr < (n > 1 ? n : 1)) return -7;
+    if (n == 0) return 0;
+    Geometry g;
+    int rc = plan(handle, m, n, TSQR_F64, &g);
+    if (rc) return rc;
+    if (g.ws_bytes > TSQR_NOALLOC_SCRATCH_BYTES) return TSQR_ERR_SCRATCH;
+    if (handle->planning_only) return TSQR_ERR_NO_DEVICE;
+    if (!handle->scratch) {
+        handle->last_hip_error = (int)hipErrorInvalidSymbol;
+        return TSQR_ERR_HIP;
+    }
+    return geqr_r<double>(handle, m, n, A, lda, R, ldr, handle->scratch, TSQR_NOALLOC_SCRATCH_BYTES, stream,
+                          TSQR_F64);
 }
 
 int tsqr_geqr_r_f32(tsqr_handle_t handle, int64_t m, int64_t n, const float* A, int64_t lda, float* R,

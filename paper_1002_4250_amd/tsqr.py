@@ -24,6 +24,8 @@ TSQR_ERR_HIP = 1
 TSQR_ERR_UNSUPPORTED = 2
 TSQR_ERR_NO_DEVICE = 3
 TSQR_ERR_ALLOC = 4
+TSQR_ERR_SCRATCH = 5
+TSQR_NOALLOC_SCRATCH_BYTES = 32 << 20
 TSQR_OPT_LEAF_ROWS = 1
 TSQR_OPT_ROWS_PER_LANE = 2
 TSQR_OPT_WAVES_PER_CU = 3
@@ -44,6 +46,7 @@ SIGNATURES = [
     ("tsqr_workspace_bytes", _i64, [_p, _i64, _i64, _i]),
     ("tsqr_geqr_r_f64", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
     ("tsqr_geqr_r_f32", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
+    ("tsqr_geqr_r_f64_noalloc", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p]),
     ("tsqr_qr_uppers_f64", _i, [_p, _i64, _p, _p, _p, _p]),
     ("tsqr_qr_uppers_f32", _i, [_p, _i64, _p, _p, _p, _p]),
     ("tsqr_batch_plan_create", _i, [_p, _i64, _i64, _pi64, _pi64, _pi64, _i, ctypes.POINTER(_p)]),
@@ -164,6 +167,10 @@ def tsqr_geqr_r_f64(handle, m, n, A, lda, R, ldr, ws, ws_bytes, stream) -> int:
 
 def tsqr_geqr_r_f32(handle, m, n, A, lda, R, ldr, ws, ws_bytes, stream) -> int:
     return lib().tsqr_geqr_r_f32(handle, m, n, A, lda, R, ldr, ws, ws_bytes, stream)
+
+
+def tsqr_geqr_r_f64_noalloc(handle, m, n, A, lda, R, ldr, stream) -> int:
+    return lib().tsqr_geqr_r_f64_noalloc(handle, m, n, A, lda, R, ldr, stream)
 
 
 def tsqr_qr_uppers_f64(handle, n, R1, R2, tau, stream) -> int:

@@ -32,10 +32,12 @@ def test_library_exports_every_declared_symbol():
 def test_header_constants_match_binding():
     text = open(HEADER).read()
     for name in ("TSQR_MAX_N", "TSQR_F64", "TSQR_F32", "TSQR_ERR_HIP", "TSQR_ERR_UNSUPPORTED",
-                 "TSQR_ERR_NO_DEVICE", "TSQR_ERR_ALLOC", "TSQR_OPT_LEAF_ROWS", "TSQR_OPT_ROWS_PER_LANE",
-                 "TSQR_OPT_WAVES_PER_CU"):
+                 "TSQR_ERR_NO_DEVICE", "TSQR_ERR_ALLOC", "TSQR_ERR_SCRATCH", "TSQR_OPT_LEAF_ROWS",
+                 "TSQR_OPT_ROWS_PER_LANE", "TSQR_OPT_WAVES_PER_CU"):
         m = re.search(r"#define\s+%s\s+(\d+)" % name, text)
         assert m and int(m.group(1)) == getattr(tsqr, name), name
+    m = re.search(r"#define\s+TSQR_NOALLOC_SCRATCH_BYTES\s+\(\(int64_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == tsqr.TSQR_NOALLOC_SCRATCH_BYTES
 
 
 @pytest.fixture
@@ -383,3 +385,29 @@ def test_binding_refuses_wrong_tensors():
         tsqr._check_flat(flat[::2], "A", 10, torch.float32, cpu)
     with pytest.raises(TypeError):
         tsqr._check_flat(flat, "A", 10, torch.float64, cpu)
+
+
+def test_noalloc_entry_point_checks_on_the_host(ph):
+    """Argument codes, the scratch limit (checked from the plan, before any
+    launch) and the planning-only handle, without a GPU."""
+    L = tsqr.lib()
+    f = L.tsqr_geqr_r_f64_noalloc
+    A, R = 4096, 8192             # placeholder addresses: nothing is launched on this handle
+    assert f(None, 10, 2, A, 10, R, 2, None) == -1
+    assert f(ph, -1, 2, A, 10, R, 2, None) == -2
+    assert f(ph, 10, -2, A, 10, R, 2, None) == -3
+    assert f(ph, 10, 2, None, 10, R, 2, None) == -4
+    assert f(ph, 10, 2, A, 9, R, 2, None) == -5
+    assert f(ph, 10, 2, A, 10, None, 2, None) == -6
+    assert f(ph, 10, 2, A, 10, R, 1, None) == -7
+    assert f(ph, 10, 0, A, 10, R, 1, None) == 0
+    assert f(ph, 1 << 22, 50, A, 1 << 22, R, 50, None) == tsqr.TSQR_ERR_NO_DEVICE
+    assert f(ph, 10, 65, A, 10, R, 65, None) == tsqr.TSQR_ERR_UNSUPPORTED
+    # every n at the largest m fits the scratch with the built-in policy ...
+    for n in (1, 16, 50, 64):
+        assert tsqr.tsqr_workspace_bytes(ph, 1 << 30, n, tsqr.TSQR_F64) <= tsqr.TSQR_NOALLOC_SCRATCH_BYTES, n
+    # ... a tiny leaf size on a large m does not
+    tsqr.tsqr_set_option(ph, tsqr.TSQR_OPT_LEAF_ROWS, 128)
+    assert f(ph, 1 << 22, 50, A, 1 << 22, R, 50, None) == tsqr.TSQR_ERR_SCRATCH
+    tsqr.tsqr_set_option(ph, tsqr.TSQR_OPT_LEAF_ROWS, 0)
+    assert b"scratch" in L.tsqr_status_string(tsqr.TSQR_ERR_SCRATCH)
