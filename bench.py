@@ -166,8 +166,10 @@ def time_q(torch, tsqr, Ad, steps, warmup, library=True):
     }
 
 
-def time_batched(torch, tsqr, inputs, steps, warmup, n=50, count=4096):
-    """The ragged batch: batched launch vs looped single-matrix calls."""
+def time_batched(torch, tsqr, inputs, steps, warmup, n=50, count=4096, single_loop=True):
+    """The ragged batch: batched launch vs looped single-matrix calls (the
+    loop, 8192 launches per pass, is skipped with single_loop=False, e.g.
+    under a counter-collecting profiler)."""
     import numpy as np
     t = time.perf_counter()
     flat, sizes, offsets = inputs.batched_uniform(count, n, 64, 65536, seed=2, dtype=np.float32)
@@ -213,6 +215,15 @@ def time_batched(torch, tsqr, inputs, steps, warmup, n=50, count=4096):
     except RuntimeError as e:
         log(f"graph capture of the batched launch failed: {e}")
 
+    if not single_loop:
+        sum_rows = int(sizes.sum())
+        tflops = 2.0 * sum_rows * n * n / (ms_batched * 1e-3) / 1e12
+        log(f"batched: {ms_batched:.3f} ms/step ({count / ms_batched * 1e3:.0f} instances/s, {tflops:.2f} TFLOP/s)")
+        del Ad, R, plan
+        torch.cuda.empty_cache()
+        return {"workload": f"ragged batch {count} instances n={n} fp32", "value": count / (ms_batched * 1e-3),
+                "unit": "instances/s", "ms_per_step": ms_batched, "tiles": tiles, "leaf_rows": L,
+                "plain_loop": None}
     # looped single-matrix calls over the same device data, one shared workspace
     h = tsqr.handle(0)
     views = [Ad[int(o):int(o) + int(m) * n].view(n, int(m)).t() for m, o in zip(sizes, offsets)]
@@ -308,14 +319,14 @@ def time_mixed(torch, tsqr, inputs, steps, warmup, batch=256, m=1 << 16, n=50):
 
     k = max(1, min(steps, 10))
     R = torch.empty((batch, n, n), dtype=torch.float64, device="cuda")
-    fb = [0]
+    flags = torch.zeros(batch, dtype=torch.int32, device="cuda")
 
     def run_mixed():
-        fb[0] = mp.run(Ad, R)[1]
+        mp.launch(Ad, R, flags)      # asynchronous: the fallback decision is taken on the device
 
     ms_mixed = timed(run_mixed, k, min(warmup, 3))
     Rm = R.cpu().numpy()
-    fallbacks = int(sum(fb[0]))
+    fallbacks = int(flags.sum().item())
     sizes = np.full(batch, m, dtype=np.int64)
     offsets = np.arange(batch, dtype=np.int64) * m * n
     p32 = tsqr.BatchPlan(sizes, offsets, n, torch.float32)
@@ -383,6 +394,8 @@ def main():
     ap.add_argument("--no-q", action="store_true")
     ap.add_argument("--no-library", action="store_true", help="skip timing torch.linalg.qr beside the Q factor")
     ap.add_argument("--no-tuning", action="store_true", help="ignore the shipped tuning table")
+    ap.add_argument("--no-single-loop", action="store_true",
+                    help="skip the loop of 4096 single-matrix calls beside the batched launch")
     ap.add_argument("--m", type=int, default=1 << 22)
     ap.add_argument("--n", type=int, default=50)
     ap.add_argument("--profile-copy-bytes", type=int, default=0,
@@ -430,7 +443,8 @@ def main():
     R32 = R32.cpu().numpy().astype(np.float64)
     del Ad32
 
-    batched = None if args.no_batched else time_batched(torch, tsqr, inputs, args.steps, args.warmup)
+    batched = None if args.no_batched else time_batched(torch, tsqr, inputs, args.steps, args.warmup,
+                                                        single_loop=not args.no_single_loop)
     mixed, mixed_data = (None, None) if args.no_mixed else time_mixed(torch, tsqr, inputs, args.steps, args.warmup)
 
     cpu = None

@@ -267,18 +267,23 @@ int tsqr_geqr_qr_f32(tsqr_handle_t handle, int64_t m, int64_t n, const float *A,
  * pass over A then forms Y = A R~^-1 and G = Y^T Y and returns
  * R = chol(G) R~, the second pass of CholeskyQR2 (Fukaya, Nakatsukasa,
  * Yanagisawa, Yamamoto 2014) with the Householder factorization as its first
- * pass.  It is accurate while kappa(A) * 2^-24 << 1.  An instance whose G is
- * not numerically positive definite (roughly kappa(A) > 1e7) is refactored
- * with the plain FP64 TSQR path from its FP32 storage and reported in
- * `fallback`.
+ * pass.  It is accurate while kappa(A) * 2^-24 << 1 and G stays numerically
+ * positive definite.  An instance whose Cholesky factorization meets a pivot
+ * that is not positive and finite (an exactly or numerically rank-deficient
+ * R~; no instance of uniform or conditioned test matrices up to kappa = 1e8 has
+ * needed it) is refactored by the plain FP64 TSQR path, which reads its FP32
+ * storage directly; that decision is taken on the device.
  *
  * Create: argument codes -1 handle, -2 batch, -3 m, -4 n, -5 lda, -6 stride_a,
- * -7 plan; the plan holds a batched FP32 plan (two small device tables).
+ * -7 plan; the plan holds two batched plans (the FP32 factorization and the
+ * FP64 fallback, both with the geometry fixed at creation: later option or
+ * tuning changes on the handle do not affect it), four small device tables.
  * Exec: R is FP64, instance b's n x n R (diag >= 0) at R + b*ldr*n;
- * `fallback` is NULL or a HOST array of `batch` ints (1 = the instance took
- * the FP64 path).  The call synchronizes `stream` once to read the Cholesky
- * flags, so it cannot be captured in a graph.  Argument codes -1 plan, -2 A,
- * -3 R, -4 ldr, -6 ws, -7 ws_bytes. */
+ * `fallback` is NULL or a DEVICE array of `batch` ints, written on `stream`
+ * (1 = the instance took the FP64 path; every instance when m = 0).  The call
+ * is asynchronous on `stream`: kernel launches only, no host synchronization,
+ * no allocation, no memset, so it can be captured in a HIP graph.  Argument
+ * codes -1 plan, -2 A, -3 R, -4 ldr, -6 ws, -7 ws_bytes. */
 int tsqr_mixed_plan_create(tsqr_handle_t handle, int64_t batch, int64_t m, int64_t n, int64_t lda,
                            int64_t stride_a, tsqr_mixed_plan_t *plan);
 int tsqr_mixed_plan_destroy(tsqr_mixed_plan_t plan);

@@ -514,8 +514,22 @@ struct tsqr_batch_plan_s {
     tsqr::BatchTile* d_tiles;
 };
 
+namespace {
+int batch_plan_make(tsqr_handle_t h, int64_t batch, int64_t n, const int64_t* m, const int64_t* a_offset,
+                    const int64_t* lda, int dtype, int force_rpl, tsqr_batch_plan_t* out);
+}
+
 int tsqr_batch_plan_create(tsqr_handle_t h, int64_t batch, int64_t n, const int64_t* m, const int64_t* a_offset,
                            const int64_t* lda, int dtype, tsqr_batch_plan_t* out)
+{
+    return batch_plan_make(h, batch, n, m, a_offset, lda, dtype, 0, out);
+}
+
+namespace {
+// The batched plan; force_rpl (if positive) fixes the rows per lane, as the
+// mixed-precision fallback (compiled at 8 rows per lane only) needs.
+int batch_plan_make(tsqr_handle_t h, int64_t batch, int64_t n, const int64_t* m, const int64_t* a_offset,
+                    const int64_t* lda, int dtype, int force_rpl, tsqr_batch_plan_t* out)
 {
     if (!h) return -1;
     if (batch < 0) return -2;
@@ -533,7 +547,7 @@ int tsqr_batch_plan_create(tsqr_handle_t h, int64_t batch, int64_t n, const int6
     }
     if (n > TSQR_MAX_N) return TSQR_ERR_UNSUPPORTED;
     Geometry g;
-    int rc = n > 0 ? plan(h, 1, n, dtype, &g, true) : 0;
+    int rc = n > 0 ? plan(h, 1, n, dtype, &g, true, force_rpl) : 0;
     if (rc) return rc;
     // the leaf size: the handle's option, else the tuning table's batched
     // entry, else 64 chunks (see plan)
@@ -603,6 +617,7 @@ int tsqr_batch_plan_create(tsqr_handle_t h, int64_t batch, int64_t n, const int6
     *out = p;
     return 0;
 }
+}  // namespace
 
 int tsqr_batch_plan_destroy(tsqr_batch_plan_t plan)
 {
@@ -646,6 +661,7 @@ int tsqr_batch_exec(tsqr_batch_plan_t plan, const void* A, void* R, int64_t ldr,
     if (plan->dtype == TSQR_F64) {
         tsqr::BatchArgs<double> a;
         a.A = static_cast<const double*>(A);
+        a.run_if = nullptr;
         a.n = (int)plan->n;
         a.inst = plan->d_inst;
         a.tiles = plan->d_tiles;
@@ -657,6 +673,7 @@ int tsqr_batch_exec(tsqr_batch_plan_t plan, const void* A, void* R, int64_t ldr,
     } else {
         tsqr::BatchArgs<float> a;
         a.A = static_cast<const float*>(A);
+        a.run_if = nullptr;
         a.n = (int)plan->n;
         a.inst = plan->d_inst;
         a.tiles = plan->d_tiles;
@@ -676,14 +693,25 @@ struct tsqr_mixed_plan_s {
     int64_t batch, m, n, lda, stride_a;
     int nc;
     tsqr_batch_plan_t inner;     // the FP32 batched factorization
+    tsqr_batch_plan_t fb;        // the FP64 fallback over the FP32 storage (8 rows per lane), fixed at creation
     int64_t rows_per_block;
     int blocks;
-    int64_t off_inner, inner_bytes, off_rt, off_rp, rp_stride, off_part, off_flags, off_a64, off_ws64, ws64_bytes,
-        ws_bytes;
+    int64_t off_inner, inner_bytes, off_rt, off_rp, rp_stride, off_part, off_flags, off_fb, fb_bytes, ws_bytes;
 };
 
 namespace {
 constexpr int64_t kMixedRowsPerBlock = 4096;
+
+hipError_t dispatch_fallback(const tsqr::BatchArgs<double, float>& a, int tiles, int nc, hipStream_t s)
+{
+    switch (nc) {
+    case 16: return tsqr::launch_batch_f64in32_16(a, tiles, s);
+    case 32: return tsqr::launch_batch_f64in32_32(a, tiles, s);
+    case 50: return tsqr::launch_batch_f64in32_50(a, tiles, s);
+    case 64: return tsqr::launch_batch_f64in32_64(a, tiles, s);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t dispatch_mixed(const tsqr::MixedArgs& a, int nc, int batch, hipStream_t s)
 {
@@ -724,12 +752,23 @@ int tsqr_mixed_plan_create(tsqr_handle_t h, int64_t batch, int64_t m, int64_t n,
     if (nc < 0) return TSQR_ERR_UNSUPPORTED;
     std::vector<int64_t> ms((size_t)batch, m), offs((size_t)batch), ldas((size_t)batch, lda);
     for (int64_t b = 0; b < batch; ++b) offs[(size_t)b] = b * stride_a;
-    tsqr_batch_plan_t inner = nullptr;
+    tsqr_batch_plan_t inner = nullptr, fb = nullptr;
     int rc = tsqr_batch_plan_create(h, batch, n, ms.data(), offs.data(), ldas.data(), TSQR_F32, &inner);
     if (rc) return rc;
+    rc = batch_plan_make(h, batch, n, ms.data(), offs.data(), ldas.data(), TSQR_F64, 8, &fb);
+    if (rc) {
+        tsqr_batch_plan_destroy(inner);
+        return rc;
+    }
+    if (n > 0 && fb->rpl != 8) {
+        tsqr_batch_plan_destroy(inner);
+        tsqr_batch_plan_destroy(fb);
+        return TSQR_ERR_UNSUPPORTED;
+    }
     tsqr_mixed_plan_s* p = new (std::nothrow) tsqr_mixed_plan_s;
     if (!p) {
         tsqr_batch_plan_destroy(inner);
+        tsqr_batch_plan_destroy(fb);
         return TSQR_ERR_ALLOC;
     }
     p->h = h;
@@ -740,12 +779,12 @@ int tsqr_mixed_plan_create(tsqr_handle_t h, int64_t batch, int64_t m, int64_t n,
     p->stride_a = stride_a;
     p->nc = nc;
     p->inner = inner;
+    p->fb = fb;
     p->rows_per_block = kMixedRowsPerBlock;
     p->blocks = (int)(m > 0 ? (m + kMixedRowsPerBlock - 1) / kMixedRowsPerBlock : 1);
     const int64_t W = gram_width(nc);
-    Geometry g64;
-    const int64_t ws64 = (n > 0 && plan(h, m, n, TSQR_F64, &g64) == 0) ? g64.ws_bytes : 0;
     p->inner_bytes = tsqr_batch_workspace_bytes(inner);
+    p->fb_bytes = tsqr_batch_workspace_bytes(fb);
     int64_t off = 0;
     p->off_inner = off;
     off += align_up(p->inner_bytes > 0 ? p->inner_bytes : 0, kAlign);
@@ -758,11 +797,8 @@ int tsqr_mixed_plan_create(tsqr_handle_t h, int64_t batch, int64_t m, int64_t n,
     off += align_up(batch * p->blocks * W * W * 8, kAlign);
     p->off_flags = off;
     off += align_up(batch * 4, kAlign);
-    p->off_a64 = off;
-    off += align_up(m * n * 8, kAlign);
-    p->off_ws64 = off;
-    p->ws64_bytes = ws64;
-    off += align_up(ws64, kAlign);
+    p->off_fb = off;
+    off += align_up(p->fb_bytes > 0 ? p->fb_bytes : 0, kAlign);
     p->ws_bytes = off;
     *out = p;
     return 0;
@@ -772,6 +808,7 @@ int tsqr_mixed_plan_destroy(tsqr_mixed_plan_t plan)
 {
     if (!plan) return 0;
     tsqr_batch_plan_destroy(plan->inner);
+    tsqr_batch_plan_destroy(plan->fb);
     delete plan;
     return 0;
 }
@@ -817,32 +854,29 @@ int tsqr_mixed_exec(tsqr_mixed_plan_t plan, const float* A, double* R, int64_t l
     a.R = R;
     a.ldr = ldr;
     a.flags = reinterpret_cast<int*>(base + plan->off_flags);
-    if (plan->m > 0) {
-        hipError_t e = dispatch_mixed(a, plan->nc, (int)plan->batch, s);
-        if (e != hipSuccess) return hip_status(plan->h, e);
-    }
-    // read the flags (one synchronization) and refactor the failed instances
-    // in FP64 from their FP32 storage
-    std::vector<int> flags((size_t)plan->batch, 1);
-    if (plan->m > 0) {
-        hipError_t e = hipMemcpyAsync(flags.data(), a.flags, sizeof(int) * flags.size(), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_status(plan->h, e);
-    }
-    double* a64 = reinterpret_cast<double*>(base + plan->off_a64);
-    const int64_t ld64 = plan->m > 1 ? plan->m : 1;
-    for (int64_t b = 0; b < plan->batch; ++b) {
-        if (!flags[(size_t)b]) continue;
-        hipError_t e = tsqr::launch_convert_f32_f64(A ? A + b * plan->stride_a : nullptr, plan->m, plan->n,
-                                                   plan->lda, a64, s);
-        if (e != hipSuccess) return hip_status(plan->h, e);
-        rc = tsqr_geqr_r_f64(plan->h, plan->m, plan->n, a64, ld64, R + b * ldr * plan->n, ldr,
-                             base + plan->off_ws64, plan->ws64_bytes, stream);
-        if (rc) return rc;
-    }
-    if (fallback)
-        for (int64_t b = 0; b < plan->batch; ++b) fallback[b] = flags[(size_t)b];
-    return 0;
+    a.flags_out = fallback;
+    hipError_t e = hipSuccess;
+    if (plan->m > 0) e = dispatch_mixed(a, plan->nc, (int)plan->batch, s);
+    if (e != hipSuccess) return hip_status(plan->h, e);
+    // the plain FP64 path over the FP32 storage for the instances whose
+    // Cholesky factorization failed (every instance when m = 0, where it gives
+    // R = 0); the other instances' workgroups exit at once
+    tsqr::BatchArgs<double, float> f;
+    char* fws = base + plan->off_fb;
+    f.A = A;
+    f.run_if = plan->m > 0 ? a.flags : nullptr;
+    f.n = (int)plan->n;
+    f.inst = plan->fb->d_inst;
+    f.tiles = plan->fb->d_tiles;
+    f.tickets = reinterpret_cast<unsigned*>(fws);
+    f.tri = reinterpret_cast<double*>(fws + plan->fb->ticket_bytes);
+    f.R = R;
+    f.ldr = ldr;
+    e = tsqr::launch_zero_u32(f.tickets, plan->fb->leaves, s);
+    if (e == hipSuccess) e = dispatch_fallback(f, (int)plan->fb->tiles, plan->nc, s);
+    if (e == hipSuccess && plan->m == 0 && fallback)
+        e = tsqr::launch_fill_u32(reinterpret_cast<unsigned*>(fallback), plan->batch, 1u, s);
+    return hip_status(plan->h, e);
 }
 
 // ---- the Q factor ------------------------------------------------------------

@@ -225,22 +225,22 @@ static __device__ float kZerosF32[256];
 __device__ __forceinline__ const double* zeros_for(const double*) { return kZerosF64; }
 __device__ __forceinline__ const float* zeros_for(const float*) { return kZerosF32; }
 
-template <typename T, int RPL>
+template <typename T, int RPL, typename TIn = T>
 struct Prefetch {
-    const T* col;        // per lane: &A(base + p, 4s + q) for the next slot s to fill
-    const T* zero;       // per lane: zero block + p
+    const TIn* col;      // per lane: &A(base + p, 4s + q) for the next slot s to fill
+    const TIn* zero;     // per lane: zero block + p
     int64_t lda4;        // uniform: 4 * lda
     int cols_left;       // per lane: n - (4s + q)
     int state;           // uniform: 0 none, 1 full chunk, 2 ragged chunk
     int rows;            // uniform: rows of the next chunk inside the leaf
 };
 
-template <typename T, int RPL>
-__device__ __forceinline__ Prefetch<T, RPL> make_prefetch(const T* A, int64_t lda, int n, int64_t base, int64_t r1,
-                                                          int q, int p)
+template <typename T, int RPL, typename TIn = T>
+__device__ __forceinline__ Prefetch<T, RPL, TIn> make_prefetch(const TIn* A, int64_t lda, int n, int64_t base,
+                                                               int64_t r1, int q, int p)
 {
     static_assert(16 * RPL <= 256, "zero block too small");
-    Prefetch<T, RPL> pf;
+    Prefetch<T, RPL, TIn> pf;
     int64_t ld = lda;
     int nn = n;
     asm volatile("" : "+s"(ld), "+s"(nn));
@@ -255,19 +255,19 @@ __device__ __forceinline__ Prefetch<T, RPL> make_prefetch(const T* A, int64_t ld
 }
 
 // Fill register slot `slot` with the next chunk's columns and advance.
-template <typename T, int RPL, int NS>
-__device__ __forceinline__ void prefetch_slot(T (&c)[RPL][NS], int slot, Prefetch<T, RPL>& pf, int p)
+template <typename T, int RPL, int NS, typename TIn>
+__device__ __forceinline__ void prefetch_slot(T (&c)[RPL][NS], int slot, Prefetch<T, RPL, TIn>& pf, int p)
 {
     if (pf.state != 0) {
-        const T* ptr = pf.cols_left > 0 ? pf.col : pf.zero;
+        const TIn* ptr = pf.cols_left > 0 ? pf.col : pf.zero;
         if (pf.state == 1) {
 #pragma unroll
-            for (int r = 0; r < RPL; ++r) c[r][slot] = ptr[16 * r];
+            for (int r = 0; r < RPL; ++r) c[r][slot] = (T)ptr[16 * r];
         } else {
 #pragma unroll
             for (int r = 0; r < RPL; ++r) {
                 const bool ok = p + 16 * r < pf.rows;
-                c[r][slot] = *(ok ? ptr + 16 * r : pf.zero + 16 * r);
+                c[r][slot] = (T)*(ok ? ptr + 16 * r : pf.zero + 16 * r);
             }
         }
     }
@@ -291,9 +291,9 @@ struct VSink {
 // Step J of R := qr([R; C]) with R packed in LDS (Rs) and C in registers.  The
 // NC steps of a chunk are unrolled at compile time so every register index is
 // static and the scheduler can overlap consecutive steps.
-template <typename T, int NC, int RPL, int J, bool WQ>
+template <typename T, int NC, int RPL, int J, bool WQ, typename TIn>
 __device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* red, int q, int p,
-                                        int kcol, int spare, Prefetch<T, RPL>& pf, const VSink<T>& vs)
+                                        int kcol, int spare, Prefetch<T, RPL, TIn>& pf, const VSink<T>& vs)
 {
     constexpr int NS = Slots<NC>::NS;
     constexpr int QJ = J % 4, SJ = J / 4;     // lane row and slot holding column J
@@ -382,12 +382,12 @@ __device__ __forceinline__ void hh_step(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* re
 
     // (e) slot SJ is finished in every lane row once its last column is the
     // pivot: it takes the next chunk's columns
-    if constexpr (QJ == 3 || J == NC - 1) prefetch_slot<T, RPL, NS>(c, SJ, pf, p);
+    if constexpr (QJ == 3 || J == NC - 1) prefetch_slot<T, RPL, NS, TIn>(c, SJ, pf, p);
 }
 
-template <typename T, int NC, int RPL, bool WQ>
+template <typename T, int NC, int RPL, bool WQ, typename TIn>
 __device__ __forceinline__ void merge_chunk(T (&c)[RPL][Slots<NC>::NS], T* Rs, T* red, int q, int p,
-                                            Prefetch<T, RPL>& pf, const VSink<T>& vs)
+                                            Prefetch<T, RPL, TIn>& pf, const VSink<T>& vs)
 {
     // the column a lane completes in the reduction, passed through an opaque
     // copy so the compiler does not precompute (and keep live) one
@@ -396,7 +396,7 @@ __device__ __forceinline__ void merge_chunk(T (&c)[RPL][Slots<NC>::NS], T* Rs, T
     asm volatile("" : "+v"(kcol));
     const int spare = Tri<NC>::kSize;      // one LDS cell past the triangle
     static_for<0, NC>([&](auto jc) {
-        hh_step<T, NC, RPL, decltype(jc)::value, WQ>(c, Rs, red, q, p, kcol, spare, pf, vs);
+        hh_step<T, NC, RPL, decltype(jc)::value, WQ, TIn>(c, Rs, red, q, p, kcol, spare, pf, vs);
     });
 }
 
@@ -503,8 +503,8 @@ __device__ __forceinline__ void triangle_to_lds(const T* __restrict__ src, T* ds
 // leaf also writes its reflectors (a.qs.V, a.qs.tau_leaf), every merge those
 // of the operator (a.qs.Vn, a.qs.tau_node), and the root the sign pattern of
 // R's diagonal as the starting block of Q (a.qs.qblk, slot 0).
-template <typename T, int NC, int RPL, bool WQ = false>
-__device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T>& a, int leaf, T* Rs, T* red)
+template <typename T, int NC, int RPL, bool WQ = false, typename TIn = T>
+__device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T, TIn>& a, int leaf, T* Rs, T* red)
 {
     constexpr int CH = 16 * RPL;                  // rows per chunk
     constexpr int NT = Tri<NC>::kSize;
@@ -527,14 +527,14 @@ __device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T>& a, int lea
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     const int k = 4 * s + q;
-                    c[r][s] = (ok && k < a.n) ? a.A[row + (int64_t)k * a.lda] : T(0);
+                    c[r][s] = (ok && k < a.n) ? (T)a.A[row + (int64_t)k * a.lda] : T(0);
                 }
             }
         }
         wave_sync();
         const int64_t nchunks = (r1 - r0 + CH - 1) / CH;
         for (int64_t t = 0; t < nchunks; ++t) {
-            Prefetch<T, RPL> pf = make_prefetch<T, RPL>(a.A, a.lda, a.n, r0 + (t + 1) * CH, r1, q, p);
+            Prefetch<T, RPL, TIn> pf = make_prefetch<T, RPL, TIn>(a.A, a.lda, a.n, r0 + (t + 1) * CH, r1, q, p);
             VSink<T> vs{};
             if constexpr (WQ) {
                 vs.V = a.qs.V;
@@ -543,7 +543,7 @@ __device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T>& a, int lea
                 vs.n = a.n;
                 vs.tau = a.qs.tau_leaf + (vs.cbase / CH) * NC;
             }
-            merge_chunk<T, NC, RPL, WQ>(c, Rs, red, q, p, pf, vs);
+            merge_chunk<T, NC, RPL, WQ, TIn>(c, Rs, red, q, p, pf, vs);
         }
     }
     wave_sync();
@@ -661,14 +661,19 @@ __global__ void __launch_bounds__(kWave) tsqr_leaf_tree_kernel(LeafTreeArgs<T> a
 // hardware dispatcher starts the long leaves early and the short ones fill
 // in.  Every instance has its own tree, so the tree of one instance overlaps
 // the leaves of the others.
-template <typename T, int NC, int RPL>
-__global__ void __launch_bounds__(kWave) tsqr_batch_kernel(BatchArgs<T> b)
+//
+// With run_if set, the workgroups of an instance whose entry is 0 exit at once
+// (the mixed-precision fallback: only instances whose correction failed are
+// refactored, decided on the device).  TIn is the storage type of A.
+template <typename T, int NC, int RPL, typename TIn = T>
+__global__ void __launch_bounds__(kWave) tsqr_batch_kernel(BatchArgs<T, TIn> b)
 {
     __shared__ T Rs[Tri<NC>::kPadded];
     __shared__ T red[LdsScratch<NC>::kElems];
     const BatchTile t = b.tiles[blockIdx.x];
+    if (b.run_if && b.run_if[t.inst] == 0) return;
     const BatchInstance in = b.inst[t.inst];
-    LeafTreeArgs<T> a;
+    LeafTreeArgs<T, TIn> a;
     a.A = b.A + in.a_off;
     a.m = in.m;
     a.lda = in.lda;
@@ -680,7 +685,7 @@ __global__ void __launch_bounds__(kWave) tsqr_batch_kernel(BatchArgs<T> b)
     a.R = b.R + (int64_t)t.inst * b.ldr * b.n;
     a.ldr = b.ldr;
     a.qs = QStore<T>{};
-    leaf_tree_body<T, NC, RPL>(a, t.leaf, Rs, red);
+    leaf_tree_body<T, NC, RPL, false, TIn>(a, t.leaf, Rs, red);
 }
 
 // ---- the paper's operator as a single-workgroup kernel -------------------------

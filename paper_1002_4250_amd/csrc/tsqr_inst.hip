@@ -48,6 +48,22 @@ hipError_t TSQR_BATCH_FN2(TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL)(const Batc
                        dim3(dev::kWave), 0, s, a);
     return hipGetLastError();
 }
+// the FP64 factorization of FP32-stored instances, in the f64 unit at 8 rows per lane
+#define TSQR_IS_F64_f64 1
+#define TSQR_IS_F64_f32 0
+#define TSQR_IS_F64_(tag) TSQR_IS_F64_##tag
+#define TSQR_IS_F64(tag) TSQR_IS_F64_(tag)
+#if TSQR_IS_F64(TSQR_INST_TAG) && TSQR_INST_RPL == 8
+#define TSQR_IN32_FN(nc) launch_batch_f64in32_##nc
+#define TSQR_IN32_FN2(nc) TSQR_IN32_FN(nc)
+hipError_t TSQR_IN32_FN2(TSQR_INST_NC)(const BatchArgs<double, float>& a, int tiles, hipStream_t s)
+{
+    if (tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL((dev::tsqr_batch_kernel<double, TSQR_INST_NC, 8, float>), dim3(tiles), dim3(dev::kWave), 0, s,
+                       a);
+    return hipGetLastError();
+}
+#endif
 #elif defined(TSQR_INST_QR)
 #define TSQR_QR_FN(kind, tag, nc, rpl) launch_##kind##_##tag##_##nc##_##rpl
 #define TSQR_QR_FN2(kind, tag, nc, rpl) TSQR_QR_FN(kind, tag, nc, rpl)
@@ -107,31 +123,25 @@ hipError_t TSQR_MIXED_FN2(TSQR_INST_NC)(const MixedArgs& a, int batch, hipStream
 #endif
 #elif defined(TSQR_INST_COMMON)
 namespace dev {
-// FP32 column-major matrix to FP64 with leading dimension m (fallback input)
-__global__ void convert_f32_f64_kernel(const float* A, int64_t m, int64_t n, int64_t lda, double* out)
-{
-    const int64_t total = m * n;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
-        const int64_t i = idx % m, j = idx / m;
-        out[idx] = (double)A[i + j * lda];
-    }
-}
-
 __global__ void zero_u32_kernel(unsigned* p, int64_t count)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0u;
 }
+
+__global__ void fill_u32_kernel(unsigned* p, int64_t count, unsigned value)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = value;
+}
 }  // namespace dev
 
-hipError_t launch_convert_f32_f64(const float* A, int64_t m, int64_t n, int64_t lda, double* out, hipStream_t s)
+hipError_t launch_fill_u32(unsigned* p, int64_t count, unsigned value, hipStream_t s)
 {
-    const int64_t total = m * n;
-    if (total <= 0) return hipSuccess;
-    int64_t blocks = (total + 255) / 256;
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(dev::convert_f32_f64_kernel, dim3((unsigned)blocks), dim3(256), 0, s, A, m, n, lda, out);
+    hipLaunchKernelGGL(dev::fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, count, value);
     return hipGetLastError();
 }
 

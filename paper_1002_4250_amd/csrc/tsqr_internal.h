@@ -21,9 +21,11 @@ struct QStore {
     T* qblk;              // per leaf: NC x NC column-major block of Q (output of the tree pass)
 };
 
-template <typename T>
+// T is the arithmetic type; TIn the storage type of A (FP32 storage factored
+// in FP64 for the mixed-precision fallback; T otherwise).
+template <typename T, typename TIn = T>
 struct LeafTreeArgs {
-    const T* A;           // m-by-n, column-major
+    const TIn* A;         // m-by-n, column-major
     int64_t m;
     int64_t lda;
     int n;
@@ -53,9 +55,10 @@ struct BatchTile {
     int32_t leaf;
 };
 
-template <typename T>
+template <typename T, typename TIn = T>
 struct BatchArgs {
-    const T* A;
+    const TIn* A;
+    const int* run_if;           // null, or per instance: factor it only where run_if[b] != 0
     int n;
     const BatchInstance* inst;   // device table
     const BatchTile* tiles;      // device table, one per workgroup
@@ -79,12 +82,22 @@ TSQR_LEAF_INSTANCES(TSQR_DECLARE_LEAF)
 TSQR_LEAF_INSTANCES(TSQR_DECLARE_BATCH)
 TSQR_LEAF_INSTANCES(TSQR_DECLARE_OCC)
 TSQR_OP_INSTANCES(TSQR_DECLARE_OP)
+// the FP64 factorization of FP32-stored instances (mixed-precision fallback),
+// one per column count at 8 rows per lane
+#define TSQR_DECLARE_BATCH_IN32(NC) \
+    hipError_t launch_batch_f64in32_##NC(const BatchArgs<double, float>& a, int tiles, hipStream_t s);
+TSQR_DECLARE_BATCH_IN32(16)
+TSQR_DECLARE_BATCH_IN32(32)
+TSQR_DECLARE_BATCH_IN32(50)
+TSQR_DECLARE_BATCH_IN32(64)
+#undef TSQR_DECLARE_BATCH_IN32
 #undef TSQR_DECLARE_LEAF
 #undef TSQR_DECLARE_BATCH
 #undef TSQR_DECLARE_OCC
 #undef TSQR_DECLARE_OP
 
 hipError_t launch_zero_u32(unsigned* p, int64_t count, hipStream_t s);
+hipError_t launch_fill_u32(unsigned* p, int64_t count, unsigned value, hipStream_t s);
 
 // Q-factor mode (FP64): the leaf+tree kernel storing its reflectors, one
 // launch per tree level top-down, then one pass over the leaves.
@@ -96,7 +109,6 @@ hipError_t launch_zero_u32(unsigned* p, int64_t count, hipStream_t s);
                                                    hipStream_t s);
 TSQR_QR_INSTANCES(TSQR_QR_INSTANCES_DECL)
 #undef TSQR_QR_INSTANCES_DECL
-hipError_t launch_convert_f32_f64(const float* A, int64_t m, int64_t n, int64_t lda, double* out, hipStream_t s);
 
 // Register blocking of G: a 10 x 10 grid of S x S blocks covers the padded
 // width W = 10 S >= NC; the 55 blocks on or above the diagonal go to lanes
@@ -123,6 +135,7 @@ struct MixedArgs {
     double* R;             // instance b's R at R + b * ldr * n
     int64_t ldr;
     int* flags;            // per instance: 0 corrected, 1 Cholesky failed
+    int* flags_out;        // null, or the caller's copy of flags
 };
 
 #define TSQR_DECLARE_MIXED(NC) hipError_t launch_mixed_##NC(const MixedArgs& a, int batch, hipStream_t s);

@@ -8,8 +8,9 @@
 // This is the second pass of CholeskyQR2 (Fukaya, Nakatsukasa, Yanagisawa and
 // Yamamoto, 2014) with the FP32 Householder factorization as the first pass.
 // The Cholesky factorization fails (a pivot that is not positive and finite)
-// when R~ is too inaccurate; the instance is then flagged for the plain FP64
-// path.
+// when R~ is too inaccurate; the instance is then flagged, and a batched FP64
+// TSQR launch over the FP32 storage, whose workgroups exit at once for
+// unflagged instances, refactors it (decided on the device, no host sync).
 //
 // Two kernels:
 //   mixed_gram_kernel   one wavefront per (row block, instance): forward
@@ -199,7 +200,10 @@ __global__ void __launch_bounds__(kWave) mixed_finish_kernel(MixedArgs a)
         for (int k = i; k < NC; ++k) s = fmadd(Rc[i + k * NC], Rtl[k + (lane < NC ? lane : 0) * NC], s);
         if (i < n && lane < n) R[i + (int64_t)lane * a.ldr] = (i <= lane) ? s : 0.0;
     }
-    if (lane == 0) a.flags[b] = good ? 0 : 1;
+    if (lane == 0) {
+        a.flags[b] = good ? 0 : 1;
+        if (a.flags_out) a.flags_out[b] = good ? 0 : 1;
+    }
 }
 
 }  // namespace dev

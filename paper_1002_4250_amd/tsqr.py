@@ -60,7 +60,7 @@ SIGNATURES = [
     ("tsqr_mixed_plan_create", _i, [_p, _i64, _i64, _i64, _i64, _i64, ctypes.POINTER(_p)]),
     ("tsqr_mixed_plan_destroy", _i, [_p]),
     ("tsqr_mixed_workspace_bytes", _i64, [_p]),
-    ("tsqr_mixed_exec", _i, [_p, _p, _p, _i64, ctypes.POINTER(ctypes.c_int), _p, _i64, _p]),
+    ("tsqr_mixed_exec", _i, [_p, _p, _p, _i64, _p, _p, _i64, _p]),
 ]
 
 _LOCK = threading.Lock()
@@ -424,7 +424,10 @@ class MixedPlan:
     device tensor (instance b at element offset b * stride).  ``run(A)``
     returns (R, fallback): R a (batch, n, n) float64 tensor whose [b] is
     instance b's R stored column-major, fallback a list of 0/1 per instance
-    (1: refactored by the FP64 path)."""
+    (1: refactored by the FP64 path), which waits for the stream.
+    ``launch(A, R, flags)`` only enqueues the work (no synchronization; the
+    per-instance flags land in the int32 device tensor ``flags``), e.g. for
+    capture in a HIP graph."""
 
     def __init__(self, batch, m, n, stride=None, lda=None, device=None, h=None):
         import torch
@@ -440,17 +443,24 @@ class MixedPlan:
         nbytes = max(tsqr_mixed_workspace_bytes(self.plan), 256)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.dev)
 
-    def run(self, A_flat, R=None):
+    def launch(self, A_flat, R, flags=None):
         torch = self.torch
         _check_flat(A_flat, "A", self.a_elems, torch.float32, self.dev)
-        if R is None:
-            R = torch.empty((self.batch, self.n, self.n), dtype=torch.float64, device=self.dev)
         _check_flat(R, "R", self.batch * self.n * self.n, torch.float64, self.dev)
-        fb = (ctypes.c_int * max(self.batch, 1))()
-        st = tsqr_mixed_exec(self.plan, A_flat.data_ptr(), R.data_ptr(), self.n, fb, self.ws.data_ptr(),
+        if flags is not None:
+            _check_flat(flags, "flags", self.batch, torch.int32, self.dev)
+        st = tsqr_mixed_exec(self.plan, A_flat.data_ptr(), R.data_ptr(), self.n,
+                             flags.data_ptr() if flags is not None else None, self.ws.data_ptr(),
                              self.ws.numel(), _stream_ptr(torch, self.dev))
         _check("tsqr_mixed_exec", st, self.h)
-        return R, [int(fb[i]) for i in range(self.batch)]
+
+    def run(self, A_flat, R=None):
+        torch = self.torch
+        if R is None:
+            R = torch.empty((self.batch, self.n, self.n), dtype=torch.float64, device=self.dev)
+        flags = torch.zeros(max(self.batch, 1), dtype=torch.int32, device=self.dev)
+        self.launch(A_flat, R, flags)
+        return R, [int(v) for v in flags[:self.batch].cpu().tolist()]
 
     def __del__(self):
         try:

@@ -61,9 +61,11 @@ def test_mixed_matches_oracle_over_kappa(m, n):
 def test_mixed_falls_back_when_cholesky_fails():
     """An exactly rank-deficient instance (a repeated column) gives a singular
     R~, so its Gram matrix cannot be factored: the instance is reported and
-    refactored by the plain FP64 path from its FP32 storage, whose result it
-    must equal bit for bit.  R is not unique past the zero pivot, so against
-    the data only the Gram identity is checked."""
+    refactored by the plain FP64 path from its FP32 storage (a batched launch
+    with leaves of 64 chunks, decided on the device), whose result it must
+    equal bit for bit: the single-matrix FP64 call on the promoted values with
+    the same leaf size takes the same steps.  R is not unique past the zero
+    pivot, so against the data only the Gram identity is checked."""
     m, n = 2048, 50
     A = inputs.conditioned(m, n, 10.0, seed=11)
     A[:, 7] = A[:, 3]
@@ -72,7 +74,12 @@ def test_mixed_falls_back_when_cholesky_fails():
     Rb, fb, _ = run_mixed(flat, 2, m, n)
     assert fb == [1, 0]
     A64 = A.astype(np.float64)
-    Rs = tsqr.geqr_r(torch.from_numpy(np.ascontiguousarray(A64.T)).cuda().t()).cpu().numpy()
+    h = tsqr.handle(0)
+    tsqr.tsqr_set_option(h, tsqr.TSQR_OPT_LEAF_ROWS, 64 * 128)
+    try:
+        Rs = tsqr.geqr_r(torch.from_numpy(np.ascontiguousarray(A64.T)).cuda().t(), h=h).cpu().numpy()
+    finally:
+        tsqr.tsqr_set_option(h, tsqr.TSQR_OPT_LEAF_ROWS, 0)
     assert np.array_equal(Rb[0].T, Rs)
     G = A64.T @ A64
     assert np.linalg.norm(Rs.T @ Rs - G) / np.linalg.norm(G) < 1e-13
@@ -136,3 +143,42 @@ def test_mixed_bitwise_reproducible_and_strided():
     for b in range(batch):
         A = np.asfortranarray(flat[b * m * n:(b + 1) * m * n].reshape(n, m).T.astype(np.float64))
         assert relF(R3[b].T, oracle.r_factor(A)) < 1e-9, b
+
+
+def test_mixed_in_hip_graph_matches_eager():
+    """The call is asynchronous (kernel launches only; the fallback decision is
+    taken on the device), so it can be captured in a HIP graph: every replay,
+    with eager work between them, equals the eager result, including an
+    exactly rank-deficient instance that takes the FP64 fallback inside the
+    graph."""
+    m, n, batch = 4096, 50, 5
+    flat, _ = inputs.conditioned_batch(batch, m, n, log10_kappa_max=8.0, seed=17)
+    B = inputs.conditioned(m, n, 10.0, seed=18)
+    B[:, 9] = B[:, 4]                              # instance 2: column 9 repeats column 4
+    flat[2 * m * n:3 * m * n] = B.T.ravel()
+    plan = tsqr.MixedPlan(batch, m, n)
+    Ad = torch.from_numpy(flat).cuda()
+    eager_R, eager_fb = plan.run(Ad)
+    torch.cuda.synchronize()
+    assert eager_fb == [0, 0, 1, 0, 0]
+    R = torch.empty_like(eager_R)
+    flags = torch.zeros(batch, dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.launch(Ad, R, flags)                  # warm up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.launch(Ad, R, flags)
+    for i in range(4):
+        R.fill_(float("nan"))
+        flags.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(R, eager_R), i
+        assert flags.cpu().tolist() == eager_fb, i
+        plan.run(Ad)                               # eager work between replays
+        torch.cuda.synchronize()
