@@ -29,6 +29,13 @@ m log-uniform in [64, 65536], n = 50, FP32) three ways: one batched launch per
 step, a Python loop of single-matrix calls, and the same loop captured once
 in a HIP graph and replayed.
 
+The ``small_instance`` object times the small case (m = 256, n = 50, FP64)
+per call back to back, per call with a host
+synchronization, and per replay of the call captured in a HIP graph.
+``host`` records the CPU model and core counts; ``cpu_baseline_all_cores`` runs
+the paper's method on every usable host core (oracle block QRs in threads,
+then the oracle's operator over a binary tree) beside the one-core oracle.
+
 Roofline: the path is bound by the FP64 vector FMA rate (arithmetic
 intensity 2n/8 = 12.5 flop/byte against a ridge of 78.6/8 = 9.8), so
 ``roofline`` reports the kernel's algorithmic 2*m*n^2 flops per launch divided
@@ -104,6 +111,91 @@ def time_plain(torch, tsqr, Ad, steps, warmup):
     ms_step = t0.elapsed_time(t1) / steps
     ms_kernel = sum(a.elapsed_time(b) for a, b in ev) / steps
     return ms_step, ms_kernel, wall, R
+
+
+def time_small(torch, tsqr, inputs, reps=200):
+    """Latency of the small instance (m = 256, n = 50, FP64, seed 0; the
+    automatic policy gives two leaves of 128 rows, so one chunk per leaf and
+    one merge): per call in a back-to-back loop (HIP events), per call with a
+    host synchronization after each (wall clock, launch overhead included),
+    and per replay of the call captured in a HIP graph."""
+    import numpy as np
+    A = inputs.uniform(256, 50, 0)
+    Ad = torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t()
+    h = tsqr.handle(0)
+    ws = tsqr.workspace(256, 50, torch.float64, h=h)
+    R = torch.empty((50, 50), dtype=torch.float64, device="cuda").t()
+
+    def call():
+        tsqr.geqr_r(Ad, R=R, ws=ws, h=h)
+
+    for _ in range(20):
+        call()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        call()
+    e1.record()
+    torch.cuda.synchronize()
+    us_loop = e0.elapsed_time(e1) / reps * 1e3
+    lat = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        call()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t)
+    us_sync = float(np.median(lat) * 1e6)
+    us_graph = None
+    try:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            call()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        ref = R.clone()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            call()
+        for _ in range(10):
+            g.replay()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        us_graph = e0.elapsed_time(e1) / reps * 1e3
+        if not torch.equal(R, ref):
+            log("small instance: graph replay differs from the eager call")
+            us_graph = None
+    except RuntimeError as e:
+        log(f"small instance: graph capture failed: {e}")
+    lr, lv = tsqr.tsqr_plan_info(h, 256, 50, tsqr.TSQR_F64)
+    log(f"small m=256 n=50 fp64: {us_loop:.1f} us/call back to back, {us_sync:.1f} us with a sync, "
+        f"graph replay {us_graph if us_graph is None else round(us_graph, 1)} us")
+    return {"workload": "m=256 n=50 fp64 uniform[-1,1) seed 0", "leaves": lv, "leaf_rows": lr,
+            "us_per_call_back_to_back": us_loop, "us_per_call_synchronized": us_sync,
+            "us_per_graph_replay": us_graph, "calls": reps}
+
+
+def host_info():
+    """CPU model and core counts of the host the benchmark runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
 
 
 def time_q(torch, tsqr, Ad, steps, warmup, library=True):
@@ -446,8 +538,10 @@ def main():
     batched = None if args.no_batched else time_batched(torch, tsqr, inputs, args.steps, args.warmup,
                                                         single_loop=not args.no_single_loop)
     mixed, mixed_data = (None, None) if args.no_mixed else time_mixed(torch, tsqr, inputs, args.steps, args.warmup)
+    small = time_small(torch, tsqr, inputs)
+    host = host_info()
 
-    cpu = None
+    cpu = cpu_all = None
     acc64 = acc32 = None
     if not args.no_cpu_baseline:
         import oracle
@@ -460,6 +554,20 @@ def main():
         cpu = {"value": reps / dt, "unit": "instances/s", "cores": 1, "kind": "oracle",
                "sample": f"the full instance m={m} n={n} fp64 seed 1 factored {reps} times ({dt:.1f} s in total, "
                          "plain Householder in C, compensated sums, one thread)"}
+        # the paper's method on every usable host core: block QRs in threads,
+        # then the operator over a binary tree (context, not the target)
+        from oracle import parallel
+        cores = max(1, min(int(host["usable_cpus"] or 1), 64))
+        parallel.tsqr_r_threads(A[:1 << 16], cores)         # warm the threads
+        t = time.perf_counter()
+        Rp = parallel.tsqr_r_threads(A, cores)
+        dtp = time.perf_counter() - t
+        cpu_all = {"value": 1.0 / dtp, "unit": "instances/s", "cores": cores, "kind": "oracle_tsqr_threads",
+                   "sample": f"the full instance m={m} n={n} fp64 seed 1 once ({dtp:.2f} s): {cores} row blocks "
+                             "factored by the oracle in parallel threads, then merged with the oracle's operator "
+                             "over a binary tree",
+                   "relF_vs_oracle": float(np.linalg.norm(Rp - Ro) / np.linalg.norm(Ro))}
+        log(f"cpu, all {cores} cores: {dtp:.2f} s per instance")
         acc64 = float(np.linalg.norm(R64 - Ro) / np.linalg.norm(Ro))
         Ro32 = oracle.r_factor(A32.astype(np.float64))
         acc32 = float(np.linalg.norm(R32 - Ro32) / np.linalg.norm(Ro32))
@@ -498,6 +606,9 @@ def main():
                      "kernel": "tsqr_leaf_tree_kernel<double,50>", "kernel_ms": ms_kernel,
                      "hbm_GBs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS},
         "cpu_baseline": cpu,
+        "cpu_baseline_all_cores": cpu_all,
+        "host": host,
+        "small_instance": small,
         "accuracy": {"fp64_relF_vs_oracle": acc64, "fp32_relF_vs_oracle": acc32,
                      "gate_fp64": 1e-10, "gate_fp32": 1e-5},
         "fp32": {"value": 1000.0 / ms_step32, "unit": "instances/s", "ms_per_step": ms_step32,

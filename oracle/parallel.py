@@ -67,3 +67,31 @@ def check_batch(flat: np.ndarray, instances, R_test=None, nproc: int | None = No
             Ro[b] = r
             g[b] = res
     return Ro, g
+
+
+def tsqr_r_threads(A, threads: int) -> np.ndarray:
+    """The paper's method on host cores: the rows of A split into `threads`
+    contiguous blocks, each block's R by the oracle's definition in its own
+    thread (the C code runs without the interpreter lock), then the block
+    triangles combined pairwise with the oracle's operator qr_uppers over a
+    binary tree (lower block on top), and the signs normalized (section 2).
+    A baseline for the GPU, not a reference: its result agrees with
+    ``oracle.r_factor`` to rounding."""
+    import concurrent.futures as cf
+
+    import oracle
+    A = np.asarray(A)
+    m, n = A.shape
+    threads = max(1, min(int(threads), max(1, m // max(n, 1))))
+    bounds = [m * i // threads for i in range(threads + 1)]
+    with cf.ThreadPoolExecutor(max_workers=threads) as pool:
+        tris = list(pool.map(lambda i: oracle.r_factor(A[bounds[i]:bounds[i + 1]]), range(threads)))
+    while len(tris) > 1:
+        nxt = []
+        for i in range(0, len(tris) - 1, 2):
+            R, _, _ = oracle.qr_uppers(tris[i], tris[i + 1])
+            nxt.append(np.triu(R))
+        if len(tris) % 2:
+            nxt.append(tris[-1])
+        tris = nxt
+    return oracle.normalize_signs(tris[0])

@@ -482,3 +482,16 @@ def test_parallel_check_batch_equals_serial_oracle():
             continue
         assert np.array_equal(Ro[b], oracle.r_factor(A)), b
         assert g[b] == oracle.gram_residual(A, Rt[b]), b
+
+
+def test_threaded_method_matches_the_definition():
+    """oracle.parallel.tsqr_r_threads (the method on host cores: block QRs
+    in threads, then the operator over a binary tree) agrees with the
+    definition to rounding, for block counts that do and do not divide m."""
+    from oracle import parallel
+    A = inputs.uniform(5003, 12, 27)
+    Ro = oracle.r_factor(A)
+    for t in (1, 2, 3, 8):
+        R = parallel.tsqr_r_threads(A, t)
+        assert relF(R, Ro) < 1e-14, t
+        assert np.all(np.tril(R, -1) == 0) and np.all(np.diag(R) >= 0), t
