@@ -168,7 +168,9 @@ __device__ __forceinline__ void lds_order()
 // 1/nrm comes from the hardware reciprocal square root refined by two Newton
 // steps, nrm = S/sqrt(S) with one Newton correction, 1/(|alpha| + nrm) from the
 // hardware reciprocal with two Newton steps: a short dependent chain instead
-// of two IEEE divisions and a square root.  A column whose sigma^2 is below
+// of two IEEE divisions and a square root.  (The FP64 hardware estimates are
+// good to about 2^-24 on gfx950; one quadratic step leaves errors of tens of
+// ulps, two reach the rounding level.)  A column whose sigma^2 is below
 // the smallest normal number gives the identity reflector.
 template <typename T>
 struct Reflector {
@@ -429,22 +431,23 @@ __device__ __forceinline__ void merge_columns(T (&v)[NC], T* Rs, T* tau_out)
         const int ridx = own ? OFF + lane - J : Tri<NC>::kSize;
         const T alpha = Rs[OFF];
         const T rjk = Rs[ridx];
+        // every lane writes one cell of row J of R1: R1(J, k) for k > J, beta
+        // for k = J (no branch), a spare cell otherwise
+        const int ridx2 = own ? ridx : ((lane == J) ? OFF : Tri<NC>::kSize);
         // the pivot column, from lane J's registers to every lane
         T x[J + 1];
 #pragma unroll
         for (int i = 0; i <= J; ++i) x[i] = bpermute(J << 2, v[i]);
-        // this lane's dot product with the pivot column (two accumulators);
-        // for lane J it is sigma^2 itself
-        T d0 = x[0] * v[0], d1 = T(0);
+        // this lane's dot product with the pivot column; for lane J it is
+        // sigma^2 itself
+        // (four partial sums keep the dependent chain short)
+        T dd[4] = {x[0] * v[0], T(0), T(0), T(0)};
 #pragma unroll
-        for (int i = 1; i <= J; ++i) {
-            if (i & 1) d1 = fmadd(x[i], v[i], d1);
-            else d0 = fmadd(x[i], v[i], d0);
-        }
-        const T d = d0 + d1;
+        for (int i = 1; i <= J; ++i) dd[i & 3] = fmadd(x[i], v[i], dd[i & 3]);
+        const T d = (dd[0] + dd[1]) + (dd[2] + dd[3]);
         const Reflector<T> h = make_reflector(alpha, lane_value(d, J));
         const T w = fmadd(h.s, d, rjk);
-        Rs[ridx] = fmadd(-h.tau, w, rjk);
+        Rs[ridx2] = own ? fmadd(-h.tau, w, rjk) : ((lane == J) ? h.beta : rjk);
         const T f = own ? h.ts * w : T(0);
 #pragma unroll
         for (int i = 0; i <= J; ++i) v[i] = fmadd(-f, x[i], v[i]);
@@ -454,7 +457,6 @@ __device__ __forceinline__ void merge_columns(T (&v)[NC], T* Rs, T* tau_out)
             for (int i = 0; i <= J; ++i) v[i] = mine ? h.s * x[i] : v[i];
             if (lane == 0) tau_out[J] = h.tau;
         }
-        if (lane == 0) Rs[OFF] = h.beta;
         lds_order();
     });
 }

@@ -59,8 +59,9 @@ def test_mixed_matches_oracle_over_kappa(m, n):
 
 
 def test_mixed_falls_back_when_cholesky_fails():
-    """An exactly rank-deficient instance (a repeated column) gives a singular
-    R~, so its Gram matrix cannot be factored: the instance is reported and
+    """An exactly rank-deficient instance (a zero column: its reflector is the
+    identity, so R~ has an exact zero on the diagonal) gives a singular R~,
+    so its Gram matrix cannot be factored: the instance is reported and
     refactored by the plain FP64 path from its FP32 storage (a batched launch
     with leaves of 64 chunks, decided on the device), whose result it must
     equal bit for bit: the single-matrix FP64 call on the promoted values with
@@ -68,7 +69,7 @@ def test_mixed_falls_back_when_cholesky_fails():
     pivot, so against the data only the Gram identity is checked."""
     m, n = 2048, 50
     A = inputs.conditioned(m, n, 10.0, seed=11)
-    A[:, 7] = A[:, 3]
+    A[:, 7] = 0.0
     B = inputs.conditioned(m, n, 10.0, seed=12)
     flat = np.concatenate([A.T.ravel(), B.T.ravel()])
     Rb, fb, _ = run_mixed(flat, 2, m, n)
@@ -149,12 +150,12 @@ def test_mixed_in_hip_graph_matches_eager():
     """The call is asynchronous (kernel launches only; the fallback decision is
     taken on the device), so it can be captured in a HIP graph: every replay,
     with eager work between them, equals the eager result, including an
-    exactly rank-deficient instance that takes the FP64 fallback inside the
-    graph."""
+    exactly rank-deficient instance (a zero column) that takes the FP64
+    fallback inside the graph."""
     m, n, batch = 4096, 50, 5
     flat, _ = inputs.conditioned_batch(batch, m, n, log10_kappa_max=8.0, seed=17)
     B = inputs.conditioned(m, n, 10.0, seed=18)
-    B[:, 9] = B[:, 4]                              # instance 2: column 9 repeats column 4
+    B[:, 9] = 0.0                                  # instance 2: a zero column
     flat[2 * m * n:3 * m * n] = B.T.ravel()
     plan = tsqr.MixedPlan(batch, m, n)
     Ad = torch.from_numpy(flat).cuda()
