@@ -696,11 +696,21 @@ struct tsqr_mixed_plan_s {
     tsqr_batch_plan_t fb;        // the FP64 fallback over the FP32 storage (8 rows per lane), fixed at creation
     int64_t rows_per_block;
     int blocks;
-    int64_t off_inner, inner_bytes, off_rt, off_rp, rp_stride, off_part, off_flags, off_fb, fb_bytes, ws_bytes;
+    int64_t off_inner, inner_bytes, off_rt, off_part, off_flags, off_fb, fb_bytes, ws_bytes;
 };
 
 namespace {
-constexpr int64_t kMixedRowsPerBlock = 4096;
+// Rows per correction workgroup: about 1024 workgroups over the whole batch
+// (four two-wavefront workgroups fit a CU at n = 50, by LDS), at least 1024
+// rows, always a multiple of the 16-row tile.
+int64_t mixed_rows_per_block(int64_t batch, int64_t m)
+{
+    constexpr int64_t kTargetBlocks = 1024;
+    const int64_t per_inst = batch > 0 ? (kTargetBlocks + batch - 1) / batch : 1;
+    int64_t rows = (m + per_inst - 1) / per_inst;
+    if (rows < 1024) rows = 1024;
+    return (rows + 15) / 16 * 16;
+}
 
 hipError_t dispatch_fallback(const tsqr::BatchArgs<double, float>& a, int tiles, int nc, hipStream_t s)
 {
@@ -727,10 +737,10 @@ hipError_t dispatch_mixed(const tsqr::MixedArgs& a, int nc, int batch, hipStream
 int gram_width(int nc)
 {
     switch (nc) {
-    case 16: return tsqr::GramTile<16>::W;
-    case 32: return tsqr::GramTile<32>::W;
-    case 50: return tsqr::GramTile<50>::W;
-    default: return tsqr::GramTile<64>::W;
+    case 16: return tsqr::MfmaGram<16>::W;
+    case 32: return tsqr::MfmaGram<32>::W;
+    case 50: return tsqr::MfmaGram<50>::W;
+    default: return tsqr::MfmaGram<64>::W;
     }
 }
 }  // namespace
@@ -780,8 +790,8 @@ int tsqr_mixed_plan_create(tsqr_handle_t h, int64_t batch, int64_t m, int64_t n,
     p->nc = nc;
     p->inner = inner;
     p->fb = fb;
-    p->rows_per_block = kMixedRowsPerBlock;
-    p->blocks = (int)(m > 0 ? (m + kMixedRowsPerBlock - 1) / kMixedRowsPerBlock : 1);
+    p->rows_per_block = mixed_rows_per_block(batch, m);
+    p->blocks = (int)(m > 0 ? (m + p->rows_per_block - 1) / p->rows_per_block : 1);
     const int64_t W = gram_width(nc);
     p->inner_bytes = tsqr_batch_workspace_bytes(inner);
     p->fb_bytes = tsqr_batch_workspace_bytes(fb);
@@ -790,9 +800,6 @@ int tsqr_mixed_plan_create(tsqr_handle_t h, int64_t batch, int64_t m, int64_t n,
     off += align_up(p->inner_bytes > 0 ? p->inner_bytes : 0, kAlign);
     p->off_rt = off;
     off += align_up(batch * n * n * 4, kAlign);
-    p->off_rp = off;
-    p->rp_stride = (int64_t)nc * (nc + 1) / 2 + nc;
-    off += align_up(batch * p->rp_stride * 8, kAlign);
     p->off_part = off;
     off += align_up(batch * p->blocks * W * W * 8, kAlign);
     p->off_flags = off;
@@ -846,8 +853,6 @@ int tsqr_mixed_exec(tsqr_mixed_plan_t plan, const float* A, double* R, int64_t l
     a.stride_a = plan->stride_a;
     a.n = (int)plan->n;
     a.Rt = Rt;
-    a.Rp = reinterpret_cast<double*>(base + plan->off_rp);
-    a.rp_stride = (int)plan->rp_stride;
     a.part = reinterpret_cast<double*>(base + plan->off_part);
     a.rows_per_block = plan->rows_per_block;
     a.blocks = plan->blocks;

@@ -111,11 +111,9 @@ hipError_t TSQR_OP_FN2(TSQR_INST_TAG, TSQR_INST_NC)(int n, TSQR_INST_TAG* R1, TS
 hipError_t TSQR_MIXED_FN2(TSQR_INST_NC)(const MixedArgs& a, int batch, hipStream_t s)
 {
     if (batch <= 0) return hipSuccess;
-    hipLaunchKernelGGL((dev::mixed_prep_kernel<TSQR_INST_NC>), dim3(batch), dim3(dev::kWave), 0, s, a);
+    hipLaunchKernelGGL((dev::mixed_gram_kernel<TSQR_INST_NC>), dim3(a.blocks, batch),
+                       dim3(dev::kGramWaves * dev::kWave), 0, s, a);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((dev::mixed_gram_kernel<TSQR_INST_NC>), dim3(a.blocks, batch), dim3(dev::kWave), 0, s, a);
-    e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((dev::mixed_finish_kernel<TSQR_INST_NC>), dim3(batch), dim3(dev::kWave), 0, s, a);
     return hipGetLastError();

@@ -110,14 +110,15 @@ hipError_t launch_fill_u32(unsigned* p, int64_t count, unsigned value, hipStream
 TSQR_QR_INSTANCES(TSQR_QR_INSTANCES_DECL)
 #undef TSQR_QR_INSTANCES_DECL
 
-// Register blocking of G: a 10 x 10 grid of S x S blocks covers the padded
-// width W = 10 S >= NC; the 55 blocks on or above the diagonal go to lanes
-// 0..54.
+// The FP64 correction on the matrix cores works on 4-column blocks (the
+// 4x4x4 FP64 instruction with four independent blocks): NB blocks cover the
+// padded width W = 4 NB >= NC, and NP block pairs I <= J make up the block
+// upper triangle of R~ and of G.
 template <int NC>
-struct GramTile {
-    static constexpr int S = (NC + 9) / 10;
-    static constexpr int W = 10 * S;
-    static constexpr int kBlocks = 55;
+struct MfmaGram {
+    static constexpr int NB = (NC + 3) / 4;
+    static constexpr int W = 4 * NB;
+    static constexpr int NP = NB * (NB + 1) / 2;
 };
 
 struct MixedArgs {
@@ -127,10 +128,8 @@ struct MixedArgs {
     int64_t stride_a;
     int n;
     const float* Rt;       // R~ of instance b at Rt + b * n * n, column-major, ld n
-    double* Rp;            // per instance: R~ in FP64 packed by columns, then 1/diag (NC values)
-    int rp_stride;         // elements per instance in Rp
     double* part;          // per (instance, row block): W x W partial Gram sums
-    int64_t rows_per_block;
+    int64_t rows_per_block;  // a multiple of 16
     int blocks;            // row blocks per instance
     double* R;             // instance b's R at R + b * ldr * n
     int64_t ldr;

@@ -13,15 +13,40 @@
 // unflagged instances, refactors it (decided on the device, no host sync).
 //
 // Two kernels:
-//   mixed_gram_kernel   one wavefront per (row block, instance): forward
-//                       substitution y = a R~^-1 for one row per lane, then
-//                       the rows' contribution to G accumulated in registers,
-//                       each lane owning an S x S block of the upper triangle
-//                       of G; the block sums go to a workspace slot.
+//   mixed_gram_kernel   one wavefront per (row block, instance), on the FP64
+//                       matrix cores: the operand table of the blocked
+//                       substitution (below) from R~ into LDS, then Y = A R~^-1
+//                       and the rows' contribution to G = Y^T Y, 16 rows at a
+//                       time; the partial G goes to a workspace slot.
 //   mixed_finish_kernel one wavefront per instance: sums the slots in a fixed
 //                       order (bit-reproducible), Cholesky with one column per
 //                       lane, R = R_c R~, sign-normalized by construction
 //                       (both factors have positive diagonals).
+//
+// The matrix-core instruction is the 4x4x4 FP64 product with four independent
+// blocks, D_b = A_b B_b + C_b (b = 0..3).  Writing lane l as 16 d2 + 4 d1 + d0,
+// it takes block d1 of each operand from the lanes with that d1, and
+//     A_b(i, k) from lane (d2 = k, d0 = i),  B_b(k, j) from lane (d2 = k, d0 = j),
+//     D_b(i, j) to lane (d2 = i, d0 = j)
+// (measured on gfx950).  So a result D can be used again as a B operand as it
+// stands, and moving it to the contraction position (d2 <-> d0) makes it
+// usable as either operand.  The four blocks are four groups of 4 rows of A,
+// so one instruction covers 16 rows; every operand below is a 4 x 4 block.
+//
+// Substitution in transposed form, over the 4-column blocks J of Y = A R~^-1:
+//     Z_J^T = A_J^T - sum_{I<J} (R~_IJ)^T Y_I^T,    Y_J^T = (R~_JJ^-1)^T Z_J^T
+// (column block J of Y R~ = A, solved with the inverse of the 4 x 4 diagonal
+// block: blocked forward substitution, as in a blocked TRSM).  Y_I^T is a D
+// result and enters the later updates as their B operand directly; the A
+// operands are the constant blocks -(R~_IJ)^T and (R~_JJ^-1)^T.  The updates
+// run right-looking (each Y_I^T goes into every later Z_J^T at once), so the
+// dependent chain is two instructions per block.  Then every Y_J^T moves its
+// rows to the contraction position (one ds_bpermute per register), and
+//     G_IJ += (Y_I)^T Y_J      for I <= J,
+// one instruction per block pair, accumulated in registers over the row block.
+// The Gram products of one tile are independent of each other and of the next
+// tile's substitution, so they are issued between the dependent steps of the
+// next tile's substitution (software pipelining over tiles).
 #pragma once
 
 #include "tsqr_device.h"
@@ -31,127 +56,177 @@ namespace tsqr {
 
 namespace dev {
 
-// block index -> (I, J), I <= J, in a 10 x 10 grid
-__device__ __forceinline__ void gram_block(int t, int& I, int& J)
+// block pairs I <= J in column order
+__host__ __device__ constexpr int pair_index(int I, int J) { return J * (J + 1) / 2 + I; }
+
+// block pair p -> (I, J), the inverse of pair_index
+__host__ __device__ constexpr int pair_col(int p)
 {
-    I = 0;
-    int left = t;
-    while (left >= 10 - I) {
-        left -= 10 - I;
-        ++I;
+    int J = 0;
+    while (pair_index(0, J + 1) <= p) ++J;
+    return J;
+}
+__host__ __device__ constexpr int pair_row(int p) { return p - pair_index(0, pair_col(p)); }
+
+// Entry (i, k) of the A operand for block pair p = (I, J), with R~ (FP32,
+// column-major, ld n) extended by the identity past column n:
+//     I < J:  -R~(4I + k, 4J + i)
+//     I = J:  X(k, i),  X = R~_JJ^-1 (4 x 4 upper triangular, by back
+//             substitution; a zero pivot gives infinities, and the Cholesky
+//             factorization then flags the instance)
+__device__ inline double substitution_operand(const float* Rt, int n, int p, int i, int k)
+{
+    auto rt = [&](int r, int c) -> double {
+        if (r > c) return 0.0;
+        return (c < n) ? (double)Rt[r + (int64_t)c * n] : (r == c ? 1.0 : 0.0);
+    };
+    const int J = pair_col(p), I = p - pair_index(0, J);
+    if (I < J) return -rt(4 * I + k, 4 * J + i);
+    // column i of X = U^-1, U = R~_JJ: X(i, i) = 1/U(i, i) and, upward,
+    // X(r, i) = -(sum_{q=r+1..i} U(r, q) X(q, i)) / U(r, r)
+    const int c0 = 4 * J;
+    double x[4] = {0.0, 0.0, 0.0, 0.0};
+    x[i] = 1.0 / rt(c0 + i, c0 + i);
+    for (int r = i - 1; r >= 0; --r) {
+        double t = 0.0;
+        for (int q = r + 1; q <= i; ++q) t += rt(c0 + r, c0 + q) * x[q];
+        x[r] = -t / rt(c0 + r, c0 + r);
     }
-    J = I + left;
+    return x[k];
 }
 
-// R~ of every instance in FP64, packed by rows ((i, j) at off(i) + j - i, as
-// for the leaf triangles), extended by the identity past column n (padding
-// columns then solve to 0), followed by the reciprocals of its diagonal.
-template <int NC>
-__global__ void __launch_bounds__(kWave) mixed_prep_kernel(MixedArgs a)
+__device__ __forceinline__ double mfma4(double a, double b, double c)
 {
-    constexpr int NT = Tri<NC>::kSize;
-    const int lane = threadIdx.x;
-    const int b = blockIdx.x;
-    const int n = a.n;
-    const float* Rt = a.Rt + (int64_t)b * n * n;
-    double* out = a.Rp + (int64_t)b * a.rp_stride;
-    for (int idx = lane; idx < NT; idx += kWave) {
-        int i = 0;
-        while (Tri<NC>::off(i + 1) <= idx) ++i;
-        const int j = i + (idx - Tri<NC>::off(i));
-        out[idx] = (j < n) ? (double)Rt[i + j * n] : (i == j ? 1.0 : 0.0);
-    }
-    for (int j = lane; j < NC; j += kWave) out[NT + j] = (j < n) ? 1.0 / (double)Rt[j + j * n] : 1.0;
+    return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
-template <int NC>
-__global__ void __launch_bounds__(kWave) mixed_gram_kernel(MixedArgs a)
+constexpr int kGramWaves = 2;
+
+// The work of one wavefront of the Gram kernel: the substitution of its own
+// tile in every iteration and, for both tiles of the iteration, the products
+// of block pairs [P0, P1).
+template <int NC, int P0, int P1>
+__device__ __forceinline__ void gram_wave(const MixedArgs& a, const double* opl,
+                                          double (&ys)[2][kGramWaves][MfmaGram<NC>::NB][kWave], int wave)
 {
-    constexpr int S = GramTile<NC>::S;
-    constexpr int W = GramTile<NC>::W;
-    constexpr int YS = W + 1;                              // LDS row stride of Y
-    constexpr int NT = Tri<NC>::kSize;
-    __shared__ double Y[kWave * YS];
-    const int lane = threadIdx.x;
+    constexpr int NB = MfmaGram<NC>::NB;
+    constexpr int W = MfmaGram<NC>::W;
+    constexpr int NQ = P1 - P0;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int d0 = lane & 3, d1 = (lane >> 2) & 3, d2 = lane >> 4;
     const int b = blockIdx.y;
     const int n = a.n;
-    // R~ is the same for every lane: read through the scalar unit, so each
-    // forward-substitution FMA takes its R~ operand from a scalar register
-    const double* __restrict__ Rp = a.Rp + (int64_t)b * a.rp_stride;
-    for (int idx = lane; idx < kWave * YS; idx += kWave) Y[idx] = 0.0;
-    wave_sync();
-
-    int I = 0, J = 0;
-    gram_block(lane < GramTile<NC>::kBlocks ? lane : 0, I, J);
-    double acc[S][S];
+    // (the LDS offset passes through an opaque copy every iteration, so the
+    // compiler reads each operand where it is used instead of hoisting all of
+    // them into registers)
+    int lofs = 4 * d0 + d2;
+    auto opnd = [&](int p) -> double { return opl[p * 16 + lofs]; };
+    double g[NQ];
 #pragma unroll
-    for (int s = 0; s < S; ++s)
-#pragma unroll
-        for (int t = 0; t < S; ++t) acc[s][t] = 0.0;
+    for (int q = 0; q < NQ; ++q) g[q] = 0.0;
 
     const float* A = a.A + (int64_t)b * a.stride_a;
     const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_block;
     const int64_t r1 = (r0 + a.rows_per_block < a.m) ? r0 + a.rows_per_block : a.m;
-    // this lane's row of the next 64-row block, loaded one block ahead
-    float nxt[NC];
-    auto load_rows = [&](int64_t base) {
-        const int64_t row = base + lane;
-        const bool ok = row < r1;
+    // Lane (d2, d1, d0) holds row 4 d1 + d0 of a 16-row tile in column 4J + d2
+    // of block J: the D layout of Z_J^T.  Columns past n read column n - 1
+    // instead (no select in the loop): they only reach padding columns of Y
+    // and padding entries of G, since R~ is the identity there and its
+    // off-diagonal blocks are zero in padding rows, and the finish kernel never
+    // reads those entries.  Block J is read from the uniform column 4 jc(J),
+    // jc(J) = min(J, jl) with jl = (n - 1)/4, at the per-lane offset of
+    // (column - 4 jc(J)) in [0, 3]: d2 for J < jl, eb from jl on.  Rows past
+    // the row block read as zero.
+    const int trow = 4 * d1 + d0;
+    const int tdst = 16 * d0 + 4 * d1 + d2;     // the d2 <-> d0 partner
+    const int jl = (n - 1) >> 2;
+    const int eb = ((4 * jl + d2 < n) ? 4 * jl + d2 : n - 1) - 4 * jl;
+    const int64_t offa = trow + (int64_t)d2 * a.lda;
+    const int64_t offb = trow + (int64_t)eb * a.lda;
+    float nxt[NB];
+    auto load_tile = [&](int64_t base) {
+        const bool ok = base + trow < r1;
 #pragma unroll
-        for (int j = 0; j < NC; ++j) {
-            const bool in = ok && j < n;
-            const float v = A[in ? row + (int64_t)j * a.lda : 0];
-            nxt[j] = in ? v : 0.0f;
+        for (int J = 0; J < NB; ++J) {
+            const int jc = J < jl ? J : jl;
+            const float* __restrict__ colp = A + base + (int64_t)(4 * jc) * a.lda;
+            const float v = colp[J < jl ? offa : offb];
+            nxt[J] = ok ? v : 0.0f;
         }
     };
-    if (r0 < r1) load_rows(r0);
-    for (int64_t base = r0; base < r1; base += kWave) {
-        double y[NC];
+    // An iteration takes 32 rows: wave w substitutes the tile at base + 16 w
+    // (rows past r1 are zero and add nothing), both tiles' Y^T go to LDS, and
+    // each wave adds both tiles' products for its block pairs.
+    int buf = 0;
+    if (r0 < r1) load_tile(r0 + 16 * wave);
+    for (int64_t base = r0; base < r1; base += kGramWaves * 16) {
+        asm volatile("" : "+v"(lofs));
+        double z[NB];
 #pragma unroll
-        for (int j = 0; j < NC; ++j) y[j] = (double)nxt[j];
-        if (base + kWave < r1) load_rows(base + kWave);
-        // y := y R~^-1, one row of R~ at a time: after step i, y_i is final
-        // and the updates of the step are independent
+        for (int J = 0; J < NB; ++J) z[J] = (double)nxt[J];
+        if (base + kGramWaves * 16 < r1) load_tile(base + kGramWaves * 16 + 16 * wave);
+        static_for<0, NB>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            z[I] = mfma4(opnd(pair_index(I, I)), z[I], 0.0);          // Y_I^T
+            static_for<I + 1, NB>([&](auto jc) {
+                constexpr int J = decltype(jc)::value;
+                z[J] = mfma4(opnd(pair_index(I, J)), z[I], z[J]);     // Z_J^T -= (R~_IJ)^T Y_I^T
+            });
+        });
 #pragma unroll
-        for (int i = 0; i < NC; ++i) {
-            const double yi = y[i] * Rp[NT + i];
-            y[i] = yi;
+        for (int I = 0; I < NB; ++I) ys[buf][wave][I][tdst] = z[I];
+        __syncthreads();
 #pragma unroll
-            for (int j = i + 1; j < NC; ++j) y[j] = fmadd(-yi, Rp[Tri<NC>::off(i) + j - i], y[j]);
+        for (int w = 0; w < kGramWaves; ++w) {
+            double t[NB];
+#pragma unroll
+            for (int I = 0; I < NB; ++I) t[I] = ys[buf][w][I][lane];
+            static_for<0, NQ>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                g[q] = mfma4(t[pair_row(P0 + q)], t[pair_col(P0 + q)], g[q]);
+            });
         }
-#pragma unroll
-        for (int j = 0; j < NC; ++j) Y[lane * YS + j] = y[j];
-        wave_sync();
-        if (lane < GramTile<NC>::kBlocks) {
-#pragma unroll 8
-            for (int r = 0; r < kWave; ++r) {
-                double yi[S], yj[S];
-#pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    yi[s] = Y[r * YS + I * S + s];
-                    yj[s] = Y[r * YS + J * S + s];
-                }
-#pragma unroll
-                for (int s = 0; s < S; ++s)
-#pragma unroll
-                    for (int t = 0; t < S; ++t) acc[s][t] = fmadd(yi[s], yj[t], acc[s][t]);
-            }
-        }
-        wave_sync();
+        buf ^= 1;
     }
-    if (lane < GramTile<NC>::kBlocks) {
-        double* out = a.part + ((int64_t)b * a.blocks + blockIdx.x) * (W * W);
-#pragma unroll
-        for (int s = 0; s < S; ++s)
-#pragma unroll
-            for (int t = 0; t < S; ++t) out[(I * S + s) * W + (J * S + t)] = acc[s][t];
-    }
+    // the four row groups (instruction blocks, d1) hold partial sums of every
+    // block of G: add them within each 16-lane row, then the lanes with d1 = 0
+    // write block (I, J) of the upper block triangle, entry (d2, d0)
+    double* out = a.part + ((int64_t)b * a.blocks + blockIdx.x) * (W * W);
+    static_for<0, NQ>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        double v = g[q];
+        v = v + dpp_mov<0x124>(v);    // row_ror:4
+        v = v + dpp_mov<0x128>(v);    // row_ror:8
+        if (d1 == 0) out[(4 * pair_row(P0 + q) + d2) * W + 4 * pair_col(P0 + q) + d0] = v;
+    });
+}
+
+template <int NC>
+__global__ void __launch_bounds__(kGramWaves * kWave) mixed_gram_kernel(MixedArgs a)
+{
+    constexpr int NB = MfmaGram<NC>::NB;
+    constexpr int NP = MfmaGram<NC>::NP;
+    constexpr int HALF = (NP + 1) / 2;
+    // the operand table, entry (i, k) of pair p at 16 p + 4 i + k
+    __shared__ double opl[NP * 16];
+    // Y^T blocks of the two tiles of an iteration (one per wave), stored at the
+    // contraction position (lane (d2, d1, d0) writes where lane (d0, d1, d2)
+    // reads), double-buffered across iterations
+    __shared__ double ys[2][kGramWaves][NB][kWave];
+    const int b = blockIdx.y;
+    const float* Rt = a.Rt + (int64_t)b * a.n * a.n;
+    for (int idx = threadIdx.x; idx < NP * 16; idx += kGramWaves * kWave)
+        opl[idx] = substitution_operand(Rt, a.n, idx >> 4, (idx >> 2) & 3, idx & 3);
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave == 0) gram_wave<NC, 0, HALF>(a, opl, ys, 0);
+    else gram_wave<NC, HALF, NP>(a, opl, ys, 1);
 }
 
 template <int NC>
 __global__ void __launch_bounds__(kWave) mixed_finish_kernel(MixedArgs a)
 {
-    constexpr int W = GramTile<NC>::W;
+    constexpr int W = MfmaGram<NC>::W;
     __shared__ double Rc[NC * NC];       // column-major, ld NC
     __shared__ double Rtl[NC * NC];      // R~ column-major, zero below the diagonal
     const int lane = threadIdx.x;
