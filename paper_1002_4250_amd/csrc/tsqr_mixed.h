@@ -13,11 +13,12 @@
 // unflagged instances, refactors it (decided on the device, no host sync).
 //
 // Two kernels:
-//   mixed_gram_kernel   one wavefront per (row block, instance), on the FP64
-//                       matrix cores: the operand table of the blocked
-//                       substitution (below) from R~ into LDS, then Y = A R~^-1
-//                       and the rows' contribution to G = Y^T Y, 16 rows at a
-//                       time; the partial G goes to a workspace slot.
+//   mixed_gram_kernel   one workgroup of two wavefronts per (row block,
+//                       instance), on the FP64 matrix cores: the operand table
+//                       of the blocked substitution (below) from R~ into LDS,
+//                       then Y = A R~^-1 and the rows' contribution to
+//                       G = Y^T Y, 32 rows at a time; the partial G goes to a
+//                       workspace slot.
 //   mixed_finish_kernel one wavefront per instance: sums the slots in a fixed
 //                       order (bit-reproducible), Cholesky with one column per
 //                       lane, R = R_c R~, sign-normalized by construction
@@ -41,12 +42,14 @@
 // operands are the constant blocks -(R~_IJ)^T and (R~_JJ^-1)^T.  The updates
 // run right-looking (each Y_I^T goes into every later Z_J^T at once), so the
 // dependent chain is two instructions per block.  Then every Y_J^T moves its
-// rows to the contraction position (one ds_bpermute per register), and
+// rows to the contraction position (a store to LDS at the partner lane's
+// index), and
 //     G_IJ += (Y_I)^T Y_J      for I <= J,
 // one instruction per block pair, accumulated in registers over the row block.
-// The Gram products of one tile are independent of each other and of the next
-// tile's substitution, so they are issued between the dependent steps of the
-// next tile's substitution (software pipelining over tiles).
+// Each of the two wavefronts substitutes its own 16-row tile and then adds,
+// for both tiles, the products of half of the block pairs, so the registers of
+// a wavefront hold half of G and two wavefronts fit a SIMD: one's dependent
+// substitution chain runs beside the other's independent Gram products.
 #pragma once
 
 #include "tsqr_device.h"
@@ -143,28 +146,30 @@ __device__ __forceinline__ void gram_wave(const MixedArgs& a, const double* opl,
     const int eb = ((4 * jl + d2 < n) ? 4 * jl + d2 : n - 1) - 4 * jl;
     const int64_t offa = trow + (int64_t)d2 * a.lda;
     const int64_t offb = trow + (int64_t)eb * a.lda;
-    float nxt[NB];
-    auto load_tile = [&](int64_t base) {
+    auto load_tile = [&](float (&dst)[NB], int64_t base) {
         const bool ok = base + trow < r1;
 #pragma unroll
         for (int J = 0; J < NB; ++J) {
             const int jc = J < jl ? J : jl;
             const float* __restrict__ colp = A + base + (int64_t)(4 * jc) * a.lda;
             const float v = colp[J < jl ? offa : offb];
-            nxt[J] = ok ? v : 0.0f;
+            dst[J] = ok ? v : 0.0f;
         }
     };
-    // An iteration takes 32 rows: wave w substitutes the tile at base + 16 w
-    // (rows past r1 are zero and add nothing), both tiles' Y^T go to LDS, and
-    // each wave adds both tiles' products for its block pairs.
+    // An iteration takes kGramWaves * 16 rows: wave w substitutes the tile at
+    // base + 16 w (rows past r1 are zero and add nothing), every tile's Y^T goes
+    // to LDS, and each wave adds every tile's products for its block pairs.
+    // Tiles are loaded two iterations ahead (two register buffers, the loop
+    // unrolled by two), which keeps enough loads in flight to cover the memory
+    // latency.
+    constexpr int64_t STEP = kGramWaves * 16;
     int buf = 0;
-    if (r0 < r1) load_tile(r0 + 16 * wave);
-    for (int64_t base = r0; base < r1; base += kGramWaves * 16) {
+    auto iteration = [&](float (&cur)[NB], int64_t base) {
         asm volatile("" : "+v"(lofs));
         double z[NB];
 #pragma unroll
-        for (int J = 0; J < NB; ++J) z[J] = (double)nxt[J];
-        if (base + kGramWaves * 16 < r1) load_tile(base + kGramWaves * 16 + 16 * wave);
+        for (int J = 0; J < NB; ++J) z[J] = (double)cur[J];
+        if (base + 2 * STEP < r1) load_tile(cur, base + 2 * STEP + 16 * wave);
         static_for<0, NB>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
             z[I] = mfma4(opnd(pair_index(I, I)), z[I], 0.0);          // Y_I^T
@@ -187,6 +192,13 @@ __device__ __forceinline__ void gram_wave(const MixedArgs& a, const double* opl,
             });
         }
         buf ^= 1;
+    };
+    float nx0[NB], nx1[NB];
+    if (r0 < r1) load_tile(nx0, r0 + 16 * wave);
+    if (r0 + STEP < r1) load_tile(nx1, r0 + STEP + 16 * wave);
+    for (int64_t base = r0; base < r1; base += 2 * STEP) {
+        iteration(nx0, base);
+        if (base + STEP < r1) iteration(nx1, base + STEP);
     }
     // the four row groups (instruction blocks, d1) hold partial sums of every
     // block of G: add them within each 16-lane row, then the lanes with d1 = 0
@@ -206,7 +218,7 @@ __global__ void __launch_bounds__(kGramWaves * kWave) mixed_gram_kernel(MixedArg
 {
     constexpr int NB = MfmaGram<NC>::NB;
     constexpr int NP = MfmaGram<NC>::NP;
-    constexpr int HALF = (NP + 1) / 2;
+    constexpr int Q = (NP + kGramWaves - 1) / kGramWaves;
     // the operand table, entry (i, k) of pair p at 16 p + 4 i + k
     __shared__ double opl[NP * 16];
     // Y^T blocks of the two tiles of an iteration (one per wave), stored at the
@@ -218,9 +230,14 @@ __global__ void __launch_bounds__(kGramWaves * kWave) mixed_gram_kernel(MixedArg
     for (int idx = threadIdx.x; idx < NP * 16; idx += kGramWaves * kWave)
         opl[idx] = substitution_operand(Rt, a.n, idx >> 4, (idx >> 2) & 3, idx & 3);
     __syncthreads();
+    // wave w owns block pairs [w Q, (w + 1) Q)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (wave == 0) gram_wave<NC, 0, HALF>(a, opl, ys, 0);
-    else gram_wave<NC, HALF, NP>(a, opl, ys, 1);
+    static_for<0, kGramWaves>([&](auto wc) {
+        constexpr int w = decltype(wc)::value;
+        constexpr int P0 = w * Q < NP ? w * Q : NP;
+        constexpr int P1 = (w + 1) * Q < NP ? (w + 1) * Q : NP;
+        if (wave == w) gram_wave<NC, P0, P1>(a, opl, ys, w);
+    });
 }
 
 template <int NC>
@@ -237,17 +254,22 @@ __global__ void __launch_bounds__(kWave) mixed_finish_kernel(MixedArgs a)
         const int i = idx % NC, j = idx / NC;
         Rtl[idx] = (i <= j && j < n) ? (double)Rt[i + j * n] : 0.0;
     }
-    // column `lane` of G (rows 0..lane), the partial sums added in block order
+    // column `lane` of G (rows 0..lane), the partial sums added in block order;
+    // a slot's NC loads are issued together (entries below the diagonal
+    // block triangle are never written and are discarded below)
     double c[NC];
-    const double* part = a.part + (int64_t)b * a.blocks * (W * W);
+#pragma unroll
+    for (int i = 0; i < NC; ++i) c[i] = 0.0;
+    const double* part = a.part + (int64_t)b * a.blocks * (W * W) + (lane < n ? lane : 0);
+    for (int w = 0; w < a.blocks; ++w) {
+#pragma unroll
+        for (int i = 0; i < NC; ++i) c[i] += part[(int64_t)w * (W * W) + i * W];
+    }
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
-        const bool in = i <= lane && lane < n;
-        double g = 0.0;
-        if (in)
-            for (int w = 0; w < a.blocks; ++w) g += part[(int64_t)w * (W * W) + i * W + lane];
         // padding columns: identity, so the factor stays nonsingular
-        c[i] = in ? g : ((i == lane && lane >= n) ? 1.0 : 0.0);
+        const bool in = i <= lane && lane < n;
+        c[i] = in ? c[i] : ((i == lane && lane >= n) ? 1.0 : 0.0);
     }
     // Cholesky G = Rc^T Rc, column `lane` of Rc in c (rows 0..lane)
     bool good = true;
