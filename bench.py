@@ -418,7 +418,19 @@ def time_mixed(torch, tsqr, inputs, steps, warmup, batch=256, m=1 << 16, n=50):
 
     ms_mixed = timed(run_mixed, k, min(warmup, 3))
     Rm = R.cpu().numpy()
+    Rtm = mp.rtilde().cpu().numpy()
     fallbacks = int(flags.sum().item())
+    # the same correction with R~ from the FP32 TSQR of a stratified sample of
+    # 4096 rows (1/16 of each instance) instead of all of A
+    sample_rows = 4096
+    ms_ = tsqr.MixedPlan(batch, m, n, sample_rows=sample_rows, seed=1)
+    Rs_d = torch.empty((batch, n, n), dtype=torch.float64, device="cuda")
+    flags_s = torch.zeros(batch, dtype=torch.int32, device="cuda")
+    ms_sampled = timed(lambda: ms_.launch(Ad, Rs_d, flags_s), k, min(warmup, 3))
+    Rs = Rs_d.cpu().numpy()
+    Rts = ms_.rtilde().cpu().numpy()
+    fallbacks_s = int(flags_s.sum().item())
+    del ms_, Rs_d
     sizes = np.full(batch, m, dtype=np.int64)
     offsets = np.arange(batch, dtype=np.int64) * m * n
     p32 = tsqr.BatchPlan(sizes, offsets, n, torch.float32)
@@ -432,7 +444,8 @@ def time_mixed(torch, tsqr, inputs, steps, warmup, batch=256, m=1 << 16, n=50):
     del A64, p64, R64, Ad
     torch.cuda.empty_cache()
     flops = 2.0 * batch * m * n * n
-    log(f"mixed: {ms_mixed:.2f} ms ({fallbacks} fallbacks); fp64 plain {ms_64:.2f} ms; fp32 alone {ms_32:.2f} ms")
+    log(f"mixed: {ms_mixed:.2f} ms ({fallbacks} fallbacks); sampled R~ ({sample_rows} rows) {ms_sampled:.2f} ms "
+        f"({fallbacks_s} fallbacks); fp64 plain {ms_64:.2f} ms; fp32 alone {ms_32:.2f} ms")
     return {
         "workload": f"{batch} instances m={m} n={n}, A = U diag(kappa^(-j/49)) V^T stored in fp32, "
                     "kappa_i = 10^(8 i/255), seeds (3, i)",
@@ -443,7 +456,12 @@ def time_mixed(torch, tsqr, inputs, steps, warmup, batch=256, m=1 << 16, n=50):
         "fp32_tsqr_alone": {"value": batch / (ms_32 * 1e-3), "ms_per_step": ms_32},
         "speedup_vs_plain_fp64": ms_64 / ms_mixed,
         "achieved_TFLOPs_2mn2": flops / (ms_mixed * 1e-3) / 1e12,
-    }, (flat, kappas, Rm, R32)
+        "sampled_rtilde": {
+            "what": f"R~ from the fp32 TSQR of a stratified sample of {sample_rows} rows (16-row blocks, "
+                    "seed 1), then the same fp64 correction over all of A",
+            "value": batch / (ms_sampled * 1e-3), "unit": "instances/s", "ms_per_step": ms_sampled,
+            "fallbacks_to_fp64": fallbacks_s, "speedup_vs_plain_fp64": ms_64 / ms_sampled},
+    }, (flat, kappas, Rm, R32, Rtm, Rs, Rts)
 
 
 def mixed_accuracy(oracle, np, data, m=1 << 16, n=50, picks=(0, 64, 128, 160, 192, 224, 255)):
@@ -454,8 +472,12 @@ def mixed_accuracy(oracle, np, data, m=1 << 16, n=50, picks=(0, 64, 128, 160, 19
     ||R^T R - A^T A||_F / ||A||_F^2 (independent of kappa).  The last two are
     the ones that separate an FP64-accurate R from an FP32 one at high kappa.
     Every instance is checked by tests/test_gpu_full_batches.py."""
-    flat, kappas, Rm, R32 = data
+    flat, kappas, Rm, R32, Rtm, Rs, Rts = data
     out = []
+
+    def kappa_y(Ro, Rt):
+        # kappa(A R~^-1) = kappa(R R~^-1), A = Q R
+        return float(np.linalg.cond(Ro @ np.linalg.inv(np.triu(Rt.T.astype(np.float64)))))
 
     def rows(X, Y):
         ny = np.linalg.norm(Y, axis=1)
@@ -471,7 +493,11 @@ def mixed_accuracy(oracle, np, data, m=1 << 16, n=50, picks=(0, 64, 128, 160, 19
                     "relF_fp32_alone": float(np.linalg.norm(R32i - Ro) / nr),
                     "row_scaled_mixed": rows(Rmi, Ro), "row_scaled_fp32_alone": rows(R32i, Ro),
                     "backward_error_mixed": oracle.gram_residual(A, Rmi),
-                    "backward_error_fp32_alone": oracle.gram_residual(A, R32i)})
+                    "backward_error_fp32_alone": oracle.gram_residual(A, R32i),
+                    "kappa_A_Rtilde_inv_mixed": kappa_y(Ro, Rtm[i]),
+                    "row_scaled_sampled": rows(Rs[i].T, Ro),
+                    "backward_error_sampled": oracle.gram_residual(A, Rs[i].T),
+                    "kappa_A_Rtilde_inv_sampled": kappa_y(Ro, Rts[i])})
     return out
 
 

@@ -291,6 +291,28 @@ int64_t tsqr_mixed_workspace_bytes(tsqr_mixed_plan_t plan);
 int tsqr_mixed_exec(tsqr_mixed_plan_t plan, const float *A, double *R, int64_t ldr, int *fallback, void *ws,
                     int64_t ws_bytes, void *stream);
 
+/* The same plan with R~ computed from a row sample instead of all of A (the
+ * sampled preconditioner: the paper's method is unchanged in the fallback,
+ * only the preconditioner of the FP64 pass is cheaper).  The sample has
+ * sample_rows rows rounded up to a multiple of 16: the m rows are cut into
+ * sample_rows/16 strata of equal length (to within one row), and from each a
+ * block of 16 contiguous rows at a uniform offset is taken, the offsets drawn
+ * from SplitMix64 (Steele, Lea and Flood 2014) of (seed, instance, stratum),
+ * so a plan always takes the same sample.  The FP32 TSQR then factors the
+ * sample, and the FP64 pass over all of A corrects as above: the result is
+ * the R of A, whatever the sample, whenever the Cholesky factorization
+ * succeeds (the sample only has to make A R~^-1 well conditioned), and the
+ * plain FP64 path otherwise.  sample_rows = 0, or a rounded count of at least
+ * m, makes it the plain mixed plan.  Argument codes as for the plain create,
+ * plus -7 sample_rows < 0, -9 plan.  Exec, destroy and workspace as above. */
+int tsqr_mixed_plan_create_sampled(tsqr_handle_t handle, int64_t batch, int64_t m, int64_t n, int64_t lda,
+                                   int64_t stride_a, int64_t sample_rows, uint64_t seed, tsqr_mixed_plan_t *plan);
+
+/* Byte offset in the workspace of R~ after tsqr_mixed_exec: FP32, instance b's
+ * n x n upper triangle at offset + 4*b*n*n, column-major, ld n (for
+ * diagnostics such as the conditioning of A R~^-1); -1 for a NULL plan. */
+int64_t tsqr_mixed_rtilde_offset(tsqr_mixed_plan_t plan);
+
 #ifdef __cplusplus
 }
 #endif

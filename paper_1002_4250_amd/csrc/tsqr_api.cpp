@@ -516,7 +516,8 @@ struct tsqr_batch_plan_s {
 
 namespace {
 int batch_plan_make(tsqr_handle_t h, int64_t batch, int64_t n, const int64_t* m, const int64_t* a_offset,
-                    const int64_t* lda, int dtype, int force_rpl, tsqr_batch_plan_t* out);
+                    const int64_t* lda, int dtype, int force_rpl, tsqr_batch_plan_t* out,
+                    int64_t leaf_rows = 0);
 }
 
 int tsqr_batch_plan_create(tsqr_handle_t h, int64_t batch, int64_t n, const int64_t* m, const int64_t* a_offset,
@@ -527,9 +528,10 @@ int tsqr_batch_plan_create(tsqr_handle_t h, int64_t batch, int64_t n, const int6
 
 namespace {
 // The batched plan; force_rpl (if positive) fixes the rows per lane, as the
-// mixed-precision fallback (compiled at 8 rows per lane only) needs.
+// mixed-precision fallback (compiled at 8 rows per lane only) needs, and
+// leaf_rows (if positive) the leaf size, rounded up to whole chunks.
 int batch_plan_make(tsqr_handle_t h, int64_t batch, int64_t n, const int64_t* m, const int64_t* a_offset,
-                    const int64_t* lda, int dtype, int force_rpl, tsqr_batch_plan_t* out)
+                    const int64_t* lda, int dtype, int force_rpl, tsqr_batch_plan_t* out, int64_t leaf_rows)
 {
     if (!h) return -1;
     if (batch < 0) return -2;
@@ -551,8 +553,9 @@ int batch_plan_make(tsqr_handle_t h, int64_t batch, int64_t n, const int64_t* m,
     if (rc) return rc;
     // the leaf size: the handle's option, else the tuning table's batched
     // entry, else 64 chunks (see plan)
-    const int64_t L = n > 0 ? g.leaf_rows
-                            : (h->leaf_rows > 0 ? align_up(h->leaf_rows, kRowsPerLaneUnit) : 64 * kRowsPerLaneUnit);
+    int64_t L = n > 0 ? g.leaf_rows
+                      : (h->leaf_rows > 0 ? align_up(h->leaf_rows, kRowsPerLaneUnit) : 64 * kRowsPerLaneUnit);
+    if (n > 0 && leaf_rows > 0) L = align_up(leaf_rows, (int64_t)kRowsPerLaneUnit * g.rpl);
     std::vector<tsqr::BatchInstance> inst((size_t)batch);
     std::vector<tsqr::BatchTile> tiles;
     std::vector<int64_t> tile_rows;
@@ -694,9 +697,11 @@ struct tsqr_mixed_plan_s {
     int nc;
     tsqr_batch_plan_t inner;     // the FP32 batched factorization
     tsqr_batch_plan_t fb;        // the FP64 fallback over the FP32 storage (8 rows per lane), fixed at creation
+    int64_t sample_rows;         // rows of the sample R~ is computed from (0: all of A)
+    uint64_t seed;
     int64_t rows_per_block;
     int blocks;
-    int64_t off_inner, inner_bytes, off_rt, off_part, off_flags, off_fb, fb_bytes, ws_bytes;
+    int64_t off_sample, off_inner, inner_bytes, off_rt, off_part, off_flags, off_fb, fb_bytes, ws_bytes;
 };
 
 namespace {
@@ -745,27 +750,32 @@ int gram_width(int nc)
 }
 }  // namespace
 
-int tsqr_mixed_plan_create(tsqr_handle_t h, int64_t batch, int64_t m, int64_t n, int64_t lda, int64_t stride_a,
-                           tsqr_mixed_plan_t* out)
+namespace {
+// Both creators: sample_rows = 0 factors all of A in FP32, otherwise a sample
+// of that many rows (rounded up to a multiple of 16; all of A when that
+// reaches m).
+int mixed_plan_make(tsqr_handle_t h, int64_t batch, int64_t m, int64_t n, int64_t lda, int64_t stride_a,
+                    int64_t sample_rows, uint64_t seed, tsqr_mixed_plan_t* out)
 {
-    if (!h) return -1;
-    if (batch < 0) return -2;
-    if (m < 0) return -3;
-    if (n < 0) return -4;
-    if (lda < (m > 1 ? m : 1)) return -5;
-    if (batch > 1 && stride_a < lda * n) return -6;
-    if (stride_a < 0) return -6;
-    if (!out) return -7;
-    *out = nullptr;
     if (n > TSQR_MAX_N) return TSQR_ERR_UNSUPPORTED;
     const int nc = n > 0 ? padded_columns(n) : 16;
     if (nc < 0) return TSQR_ERR_UNSUPPORTED;
-    std::vector<int64_t> ms((size_t)batch, m), offs((size_t)batch), ldas((size_t)batch, lda);
-    for (int64_t b = 0; b < batch; ++b) offs[(size_t)b] = b * stride_a;
+    int64_t srows = (sample_rows + 15) / 16 * 16;
+    if (srows >= m) srows = 0;
+    // the FP32 factorization runs over A itself, or over the sample buffer
+    // (instance b's s x n sample at b*s*n in it, ld s)
+    const int64_t im = srows ? srows : m, ilda = srows ? srows : lda;
+    std::vector<int64_t> ms((size_t)batch, im), offs((size_t)batch), ldas((size_t)batch, ilda);
+    for (int64_t b = 0; b < batch; ++b) offs[(size_t)b] = srows ? b * srows * n : b * stride_a;
+    std::vector<int64_t> fms((size_t)batch, m), foffs((size_t)batch), fldas((size_t)batch, lda);
+    for (int64_t b = 0; b < batch; ++b) foffs[(size_t)b] = b * stride_a;
     tsqr_batch_plan_t inner = nullptr, fb = nullptr;
-    int rc = tsqr_batch_plan_create(h, batch, n, ms.data(), offs.data(), ldas.data(), TSQR_F32, &inner);
+    // a sample is short: its leaves are sized so the batch has about 2048 of
+    // them (every SIMD busy) instead of the batched default
+    const int64_t sample_leaf = srows ? (batch * srows + 2047) / 2048 : 0;
+    int rc = batch_plan_make(h, batch, n, ms.data(), offs.data(), ldas.data(), TSQR_F32, 0, &inner, sample_leaf);
     if (rc) return rc;
-    rc = batch_plan_make(h, batch, n, ms.data(), offs.data(), ldas.data(), TSQR_F64, 8, &fb);
+    rc = batch_plan_make(h, batch, n, fms.data(), foffs.data(), fldas.data(), TSQR_F64, 8, &fb);
     if (rc) {
         tsqr_batch_plan_destroy(inner);
         return rc;
@@ -790,12 +800,16 @@ int tsqr_mixed_plan_create(tsqr_handle_t h, int64_t batch, int64_t m, int64_t n,
     p->nc = nc;
     p->inner = inner;
     p->fb = fb;
+    p->sample_rows = srows;
+    p->seed = seed;
     p->rows_per_block = mixed_rows_per_block(batch, m);
     p->blocks = (int)(m > 0 ? (m + p->rows_per_block - 1) / p->rows_per_block : 1);
     const int64_t W = gram_width(nc);
     p->inner_bytes = tsqr_batch_workspace_bytes(inner);
     p->fb_bytes = tsqr_batch_workspace_bytes(fb);
     int64_t off = 0;
+    p->off_sample = off;
+    off += align_up(batch * srows * n * 4, kAlign);
     p->off_inner = off;
     off += align_up(p->inner_bytes > 0 ? p->inner_bytes : 0, kAlign);
     p->off_rt = off;
@@ -809,6 +823,44 @@ int tsqr_mixed_plan_create(tsqr_handle_t h, int64_t batch, int64_t m, int64_t n,
     p->ws_bytes = off;
     *out = p;
     return 0;
+}
+}  // namespace
+
+int tsqr_mixed_plan_create(tsqr_handle_t h, int64_t batch, int64_t m, int64_t n, int64_t lda, int64_t stride_a,
+                           tsqr_mixed_plan_t* out)
+{
+    if (!h) return -1;
+    if (batch < 0) return -2;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (lda < (m > 1 ? m : 1)) return -5;
+    if (batch > 1 && stride_a < lda * n) return -6;
+    if (stride_a < 0) return -6;
+    if (!out) return -7;
+    *out = nullptr;
+    return mixed_plan_make(h, batch, m, n, lda, stride_a, 0, 0, out);
+}
+
+int tsqr_mixed_plan_create_sampled(tsqr_handle_t h, int64_t batch, int64_t m, int64_t n, int64_t lda,
+                                   int64_t stride_a, int64_t sample_rows, uint64_t seed, tsqr_mixed_plan_t* out)
+{
+    if (!h) return -1;
+    if (batch < 0) return -2;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (lda < (m > 1 ? m : 1)) return -5;
+    if (batch > 1 && stride_a < lda * n) return -6;
+    if (stride_a < 0) return -6;
+    if (sample_rows < 0) return -7;
+    if (!out) return -9;
+    *out = nullptr;
+    return mixed_plan_make(h, batch, m, n, lda, stride_a, sample_rows, seed, out);
+}
+
+int64_t tsqr_mixed_rtilde_offset(tsqr_mixed_plan_t plan)
+{
+    if (!plan) return -1;
+    return plan->off_rt;
 }
 
 int tsqr_mixed_plan_destroy(tsqr_mixed_plan_t plan)
@@ -843,7 +895,22 @@ int tsqr_mixed_exec(tsqr_mixed_plan_t plan, const float* A, double* R, int64_t l
     float* Rt = reinterpret_cast<float*>(base + plan->off_rt);
     int rc = 0;
     if (plan->m > 0) {
-        rc = tsqr_batch_exec(plan->inner, A, Rt, plan->n, base + plan->off_inner, plan->inner_bytes, stream);
+        const float* src = A;
+        if (plan->sample_rows) {
+            tsqr::SampleArgs sa;
+            sa.A = A;
+            sa.m = plan->m;
+            sa.lda = plan->lda;
+            sa.stride_a = plan->stride_a;
+            sa.n = (int)plan->n;
+            sa.S = reinterpret_cast<float*>(base + plan->off_sample);
+            sa.s = plan->sample_rows;
+            sa.seed = plan->seed;
+            hipError_t e = tsqr::launch_mixed_sample(sa, (int)plan->batch, s);
+            if (e != hipSuccess) return hip_status(plan->h, e);
+            src = sa.S;
+        }
+        rc = tsqr_batch_exec(plan->inner, src, Rt, plan->n, base + plan->off_inner, plan->inner_bytes, stream);
         if (rc) return rc;
     }
     tsqr::MixedArgs a;

@@ -132,7 +132,44 @@ __global__ void fill_u32_kernel(unsigned* p, int64_t count, unsigned value)
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = value;
 }
+
+// SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014): the output function applied to a counter.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x)
+{
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+// Workgroup (k, b) copies block k of instance b's sample: stratum k holds rows
+// [k q + min(k, r), ...) of length q + [k < r] (m = nb q + r, nb = s/16), and
+// the block starts at a uniform offset in [0, length - 16] drawn from
+// splitmix64 of (seed, b, k).  Lane t copies row t % 16 of the block in
+// columns t/16, t/16 + 4, ...
+__global__ void __launch_bounds__(64) mixed_sample_kernel(SampleArgs a)
+{
+    const int64_t nb = a.s / 16, k = blockIdx.x;
+    const int b = blockIdx.y;
+    const int64_t q = a.m / nb, r = a.m % nb;
+    const int64_t lo = k * q + (k < r ? k : r);
+    const int64_t len = q + (k < r ? 1 : 0);
+    const uint64_t h = splitmix64(a.seed ^ ((uint64_t)b << 32) ^ (uint64_t)k);
+    const int64_t start = lo + (int64_t)(h % (uint64_t)(len - 15));
+    const int t = threadIdx.x;
+    const float* src = a.A + (int64_t)b * a.stride_a + start + (t & 15);
+    float* dst = a.S + (int64_t)b * a.s * a.n + 16 * k + (t & 15);
+    for (int c = t >> 4; c < a.n; c += 4) dst[(int64_t)c * a.s] = src[(int64_t)c * a.lda];
+}
 }  // namespace dev
+
+hipError_t launch_mixed_sample(const SampleArgs& a, int batch, hipStream_t s)
+{
+    if (batch <= 0 || a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dev::mixed_sample_kernel, dim3((unsigned)(a.s / 16), batch), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_u32(unsigned* p, int64_t count, unsigned value, hipStream_t s)
 {

@@ -97,6 +97,20 @@ TSQR_DECLARE_BATCH_IN32(64)
 #undef TSQR_DECLARE_OP
 
 hipError_t launch_zero_u32(unsigned* p, int64_t count, hipStream_t s);
+
+// Row sample of every instance for the sampled preconditioner: rows blocks of
+// 16 contiguous rows, one block drawn uniformly inside each of s/16 equal
+// strata of the m rows, copied to S (instance b's s x n sample at S + b*s*n,
+// column-major, ld s).  s is a multiple of 16 with 16 <= s < m.
+struct SampleArgs {
+    const float* A;
+    int64_t m, lda, stride_a;
+    int n;
+    float* S;
+    int64_t s;
+    uint64_t seed;
+};
+hipError_t launch_mixed_sample(const SampleArgs& a, int batch, hipStream_t s);
 hipError_t launch_fill_u32(unsigned* p, int64_t count, unsigned value, hipStream_t s);
 
 // Q-factor mode (FP64): the leaf+tree kernel storing its reflectors, one

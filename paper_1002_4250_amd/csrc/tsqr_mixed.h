@@ -8,9 +8,12 @@
 // This is the second pass of CholeskyQR2 (Fukaya, Nakatsukasa, Yanagisawa and
 // Yamamoto, 2014) with the FP32 Householder factorization as the first pass.
 // The Cholesky factorization fails (a pivot that is not positive and finite)
-// when R~ is too inaccurate; the instance is then flagged, and a batched FP64
-// TSQR launch over the FP32 storage, whose workgroups exit at once for
-// unflagged instances, refactors it (decided on the device, no host sync).
+// when R~ is too inaccurate, and R~ is not trusted either when the bound
+// ||R_c||_F ||R_c^-1||_F on kappa(A R~^-1) exceeds 1e4; the instance is then
+// flagged, and a batched FP64 TSQR launch over the FP32 storage, whose
+// workgroups exit at once for unflagged instances, refactors it (decided on
+// the device, no host sync).  R~ may also come from the FP32 TSQR of a row
+// sample (the sampled plan): the correction is the same.
 //
 // Two kernels:
 //   mixed_gram_kernel   one workgroup of two wavefronts per (row block,
@@ -21,8 +24,9 @@
 //                       workspace slot.
 //   mixed_finish_kernel one wavefront per instance: sums the slots in a fixed
 //                       order (bit-reproducible), Cholesky with one column per
-//                       lane, R = R_c R~, sign-normalized by construction
-//                       (both factors have positive diagonals).
+//                       lane, a bound on kappa(A R~^-1), R = R_c R~,
+//                       sign-normalized by construction (both factors have
+//                       positive diagonals).
 //
 // The matrix-core instruction is the 4x4x4 FP64 product with four independent
 // blocks, D_b = A_b B_b + C_b (b = 0..3).  Writing lane l as 16 d2 + 4 d1 + d0,
@@ -240,6 +244,10 @@ __global__ void __launch_bounds__(kGramWaves * kWave) mixed_gram_kernel(MixedArg
     });
 }
 
+// bound on ||Rc||_F ||Rc^-1||_F (>= kappa_2(A R~^-1)) for a trusted correction;
+// an FP32 R~ of a matrix with kappa(A) <= 1e8 gives about n (1 + kappa(A) 2^-24)
+constexpr double kMaxKappaY = 1e4;
+
 template <int NC>
 __global__ void __launch_bounds__(kWave) mixed_finish_kernel(MixedArgs a)
 {
@@ -288,6 +296,33 @@ __global__ void __launch_bounds__(kWave) mixed_finish_kernel(MixedArgs a)
     for (int i = 0; i < NC; ++i)
         if (lane < NC) Rc[i + lane * NC] = c[i];
     wave_sync();
+    // Y = A R~^-1 = Q Rc, so kappa_2(Y) = kappa_2(Rc) <= ||Rc||_F ||Rc^-1||_F.
+    // Past kMaxKappaY the correction is not trusted (its Gram matrix carries
+    // a relative error of order kappa(Y)^2 u in its smallest directions) and
+    // the instance takes the FP64 path as well.  Column `lane` of X = Rc^-1 by
+    // back substitution against the rows of Rc in LDS; padding columns are
+    // left out of both norms.
+    {
+        double sr = 0.0, sx = 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) sr = fmadd(c[i], c[i], sr);
+        double x[NC];
+#pragma unroll
+        for (int i = NC - 1; i >= 0; --i) {
+            double t = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = i + 1; k < NC; ++k) t = fmadd(-Rc[i + k * NC], x[k], t);
+            x[i] = (i <= lane) ? t / Rc[i + i * NC] : 0.0;
+            sx = fmadd(x[i], x[i], sx);
+        }
+        if (lane >= n) sx = sr = 0.0;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            sx += __shfl_xor(sx, off);
+            sr += __shfl_xor(sr, off);
+        }
+        good = good && (sr * sx <= kMaxKappaY * kMaxKappaY);
+    }
     // R = Rc R~, column `lane`: R(i, lane) = sum_{k >= i} Rc(i, k) R~(k, lane)
     double* R = a.R + (int64_t)b * a.ldr * n;
 #pragma unroll

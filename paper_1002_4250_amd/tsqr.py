@@ -61,6 +61,8 @@ SIGNATURES = [
     ("tsqr_mixed_plan_destroy", _i, [_p]),
     ("tsqr_mixed_workspace_bytes", _i64, [_p]),
     ("tsqr_mixed_exec", _i, [_p, _p, _p, _i64, _p, _p, _i64, _p]),
+    ("tsqr_mixed_plan_create_sampled", _i, [_p, _i64, _i64, _i64, _i64, _i64, _i64, ctypes.c_uint64, ctypes.POINTER(_p)]),
+    ("tsqr_mixed_rtilde_offset", _i64, [_p]),
 ]
 
 _LOCK = threading.Lock()
@@ -404,6 +406,21 @@ def tsqr_mixed_plan_create(handle, batch, m, n, lda, stride_a) -> int:
     return plan.value
 
 
+def tsqr_mixed_plan_create_sampled(handle, batch, m, n, lda, stride_a, sample_rows, seed) -> int:
+    plan = ctypes.c_void_p()
+    st = lib().tsqr_mixed_plan_create_sampled(handle, int(batch), int(m), int(n), int(lda), int(stride_a),
+                                              int(sample_rows), int(seed) & (2**64 - 1), ctypes.byref(plan))
+    _check("tsqr_mixed_plan_create_sampled", st, handle)
+    return plan.value
+
+
+def tsqr_mixed_rtilde_offset(plan) -> int:
+    v = lib().tsqr_mixed_rtilde_offset(plan)
+    if v < 0:
+        raise TsqrError("tsqr_mixed_rtilde_offset", int(v))
+    return int(v)
+
+
 def tsqr_mixed_plan_destroy(plan) -> None:
     lib().tsqr_mixed_plan_destroy(plan)
 
@@ -427,9 +444,11 @@ class MixedPlan:
     (1: refactored by the FP64 path), which waits for the stream.
     ``launch(A, R, flags)`` only enqueues the work (no synchronization; the
     per-instance flags land in the int32 device tensor ``flags``), e.g. for
-    capture in a HIP graph."""
+    capture in a HIP graph.  With ``sample_rows`` > 0 the FP32 factorization
+    runs on a stratified row sample of that size (``seed`` picks it) instead
+    of all of A; ``rtilde()`` returns the FP32 R~ of the last call."""
 
-    def __init__(self, batch, m, n, stride=None, lda=None, device=None, h=None):
+    def __init__(self, batch, m, n, stride=None, lda=None, device=None, h=None, sample_rows=0, seed=0):
         import torch
         self.torch = torch
         self.dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
@@ -439,7 +458,11 @@ class MixedPlan:
         stride = lda * self.n if stride is None else int(stride)
         # elements of A the instances span
         self.a_elems = (self.batch - 1) * stride + (self.n - 1) * lda + self.m if self.batch and self.n and self.m else 0
-        self.plan = tsqr_mixed_plan_create(self.h, self.batch, self.m, self.n, lda, stride)
+        if sample_rows:
+            self.plan = tsqr_mixed_plan_create_sampled(self.h, self.batch, self.m, self.n, lda, stride,
+                                                       sample_rows, seed)
+        else:
+            self.plan = tsqr_mixed_plan_create(self.h, self.batch, self.m, self.n, lda, stride)
         nbytes = max(tsqr_mixed_workspace_bytes(self.plan), 256)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.dev)
 
@@ -461,6 +484,14 @@ class MixedPlan:
         flags = torch.zeros(max(self.batch, 1), dtype=torch.int32, device=self.dev)
         self.launch(A_flat, R, flags)
         return R, [int(v) for v in flags[:self.batch].cpu().tolist()]
+
+    def rtilde(self):
+        """R~ of the last call, a (batch, n, n) float32 view of the workspace
+        whose [b] is instance b's R~ stored column-major (read after the
+        stream has finished the call)."""
+        off = tsqr_mixed_rtilde_offset(self.plan)
+        count = self.batch * self.n * self.n
+        return self.ws[off:off + 4 * count].view(self.torch.float32).view(self.batch, self.n, self.n)
 
     def __del__(self):
         try:

@@ -235,10 +235,14 @@ def test_mixed_plan_checks_and_workspace(ph):
     p = tsqr.tsqr_mixed_plan_create(ph, 3, 10000, 50, 10000, 500000)
     try:
         need = tsqr.tsqr_mixed_workspace_bytes(p)
-        # FP32 batch workspace + R~ + Gram slots (3 blocks of 4096 rows, 50x50)
-        # + flags + the FP64 fallback's batched workspace (a triangle per leaf);
-        # no FP64 copy of any instance (the fallback reads the FP32 storage)
-        assert 3 * 3 * 50 * 50 * 8 + 3 * 1275 * 8 < need < 10000 * 50 * 8
+        # FP32 batch workspace + R~ + Gram slots (one 52 x 52 slot per
+        # workgroup) + flags + the FP64 fallback's batched workspace (a
+        # triangle per leaf); no FP64 copy of any instance (the fallback reads
+        # the FP32 storage)
+        assert 3 * 52 * 52 * 8 + 3 * 1275 * 8 < need < 10000 * 50 * 8
+        # R~ sits past the FP32 workspace, inside the workspace
+        off = tsqr.tsqr_mixed_rtilde_offset(p)
+        assert 0 <= off and off + 3 * 50 * 50 * 4 <= need
         buf = ctypes.create_string_buffer(need + 512)
         ws = (ctypes.addressof(buf) + 255) // 256 * 256
         assert L.tsqr_mixed_exec(None, 1, 1, 50, None, ws, need, None) == -1
@@ -251,6 +255,37 @@ def test_mixed_plan_checks_and_workspace(ph):
     finally:
         tsqr.tsqr_mixed_plan_destroy(p)
     assert L.tsqr_mixed_workspace_bytes(None) == -1
+    assert L.tsqr_mixed_rtilde_offset(None) == -1
+
+
+def test_sampled_mixed_plan_checks_and_workspace(ph):
+    L = tsqr.lib()
+    out = ctypes.c_void_p()
+    args = (2, 100, 8, 100, 800)
+    assert L.tsqr_mixed_plan_create_sampled(None, *args, 32, 1, ctypes.byref(out)) == -1
+    assert L.tsqr_mixed_plan_create_sampled(ph, -1, 100, 8, 100, 800, 32, 1, ctypes.byref(out)) == -2
+    assert L.tsqr_mixed_plan_create_sampled(ph, 2, -1, 8, 100, 800, 32, 1, ctypes.byref(out)) == -3
+    assert L.tsqr_mixed_plan_create_sampled(ph, 2, 100, -1, 100, 800, 32, 1, ctypes.byref(out)) == -4
+    assert L.tsqr_mixed_plan_create_sampled(ph, 2, 100, 8, 99, 800, 32, 1, ctypes.byref(out)) == -5
+    assert L.tsqr_mixed_plan_create_sampled(ph, 2, 100, 8, 100, 799, 32, 1, ctypes.byref(out)) == -6
+    assert L.tsqr_mixed_plan_create_sampled(ph, *args, -1, 1, ctypes.byref(out)) == -7
+    assert L.tsqr_mixed_plan_create_sampled(ph, *args, 32, 1, None) == -9
+    full = tsqr.tsqr_mixed_plan_create(ph, 4, 65536, 50, 65536, 65536 * 50)
+    samp = tsqr.tsqr_mixed_plan_create_sampled(ph, 4, 65536, 50, 65536, 65536 * 50, 4000, 7)
+    # a sample of at least m rows (after rounding to 16) is the plain plan
+    same = tsqr.tsqr_mixed_plan_create_sampled(ph, 4, 65536, 50, 65536, 65536 * 50, 65530, 7)
+    try:
+        wf = tsqr.tsqr_mixed_workspace_bytes(full)
+        ws_ = tsqr.tsqr_mixed_workspace_bytes(samp)
+        assert tsqr.tsqr_mixed_workspace_bytes(same) == wf
+        # the sample buffer (4 x 4000 x 50 FP32) is added; the FP32
+        # factorization of the samples (short leaves, a triangle each) needs
+        # at most a few MB more
+        assert ws_ >= 4 * 4000 * 50 * 4
+        assert ws_ < wf + 4 * 4000 * 50 * 4 + (4 << 20)
+    finally:
+        for p in (full, samp, same):
+            tsqr.tsqr_mixed_plan_destroy(p)
 
 
 def test_qr_workspace_query(ph):
