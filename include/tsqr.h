@@ -226,6 +226,15 @@ int64_t tsqr_batch_workspace_bytes(tsqr_batch_plan_t plan);
 /* Tiles (workgroups), leaves over all instances and rows per leaf. */
 int tsqr_batch_plan_info(tsqr_batch_plan_t plan, int64_t *tiles, int64_t *leaves, int64_t *leaf_rows);
 
+/* The schedule the plan launches, copied to host arrays (for checks; the
+ * device copies are what exec uses).  inst: 7 values per instance b at
+ * inst[7b]: element offset of A, m, lda, leaf rows, leaf count, index of its
+ * first tree counter, element offset of its first triangle slot.  tiles: 2
+ * values per workgroup t in launch order at tiles[2t]: (instance, leaf),
+ * longest leaves first, ties in instance order.  Either pointer may be NULL
+ * (sizes from tsqr_batch_plan_info).  Returns 0, or -1 for a NULL plan. */
+int tsqr_batch_plan_schedule(tsqr_batch_plan_t plan, int64_t *inst, int64_t *tiles);
+
 /* R of every instance: instance b's n-by-n R (diag >= 0, column-major,
  * leading dimension ldr >= n) is written at R + b*ldr*n elements.  A and R
  * are device pointers of the plan's element type; ws as for tsqr_geqr_r_*.

@@ -512,6 +512,8 @@ struct tsqr_batch_plan_s {
     int64_t ws_bytes;
     tsqr::BatchInstance* d_inst;
     tsqr::BatchTile* d_tiles;
+    std::vector<tsqr::BatchInstance> h_inst;   // host copies of the two tables
+    std::vector<tsqr::BatchTile> h_tiles;
 };
 
 namespace {
@@ -617,10 +619,37 @@ int batch_plan_make(tsqr_handle_t h, int64_t batch, int64_t n, const int64_t* m,
             return TSQR_ERR_ALLOC;
         }
     }
+    p->h_inst = std::move(inst);
+    p->h_tiles = std::move(sorted);
     *out = p;
     return 0;
 }
 }  // namespace
+
+int tsqr_batch_plan_schedule(tsqr_batch_plan_t plan, int64_t* inst, int64_t* tiles)
+{
+    if (!plan) return -1;
+    if (inst) {
+        for (size_t b = 0; b < plan->h_inst.size(); ++b) {
+            const tsqr::BatchInstance& in = plan->h_inst[b];
+            int64_t* o = inst + 7 * b;
+            o[0] = in.a_off;
+            o[1] = in.m;
+            o[2] = in.lda;
+            o[3] = in.leaf_rows;
+            o[4] = in.leaves;
+            o[5] = in.ticket_off;
+            o[6] = in.tri_off;
+        }
+    }
+    if (tiles) {
+        for (size_t t = 0; t < plan->h_tiles.size(); ++t) {
+            tiles[2 * t] = plan->h_tiles[t].inst;
+            tiles[2 * t + 1] = plan->h_tiles[t].leaf;
+        }
+    }
+    return 0;
+}
 
 int tsqr_batch_plan_destroy(tsqr_batch_plan_t plan)
 {

@@ -61,6 +61,7 @@ SIGNATURES = [
     ("tsqr_mixed_plan_destroy", _i, [_p]),
     ("tsqr_mixed_workspace_bytes", _i64, [_p]),
     ("tsqr_mixed_exec", _i, [_p, _p, _p, _i64, _p, _p, _i64, _p]),
+    ("tsqr_batch_plan_schedule", _i, [_p, _p, _p]),
     ("tsqr_mixed_plan_create_sampled", _i, [_p, _i64, _i64, _i64, _i64, _i64, _i64, ctypes.c_uint64, ctypes.POINTER(_p)]),
     ("tsqr_mixed_rtilde_offset", _i64, [_p]),
 ]
@@ -347,6 +348,20 @@ def tsqr_batch_plan_info(plan):
     t, l, r = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     _check("tsqr_batch_plan_info", lib().tsqr_batch_plan_info(plan, ctypes.byref(t), ctypes.byref(l), ctypes.byref(r)))
     return t.value, l.value, r.value
+
+
+def tsqr_batch_plan_schedule(plan, batch):
+    """(inst, tiles): int64 arrays of shape (batch, 7) and (tiles, 2), the
+    schedule of a plan made for `batch` instances, as
+    ``tsqr_batch_plan_schedule`` documents it."""
+    import numpy as np
+    t, _, _ = tsqr_batch_plan_info(plan)
+    inst = np.zeros((int(batch), 7), dtype=np.int64)
+    tiles = np.zeros((t, 2), dtype=np.int64)
+    _check("tsqr_batch_plan_schedule",
+           lib().tsqr_batch_plan_schedule(plan, inst.ctypes.data if inst.size else None,
+                                          tiles.ctypes.data if tiles.size else None))
+    return inst, tiles
 
 
 def tsqr_batch_exec(plan, A, R, ldr, ws, ws_bytes, stream) -> int:

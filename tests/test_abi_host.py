@@ -168,6 +168,57 @@ def test_batch_plan_tiles_and_workspace(ph):
         tsqr.tsqr_batch_plan_destroy(p)
 
 
+def _expected_schedule(sizes, offsets, ldas, L, tri):
+    """The schedule enumerated from its definition: instance b is cut into
+    max(1, ceil(m_b / L)) leaves of L rows (the last one ragged); its tree
+    counters and triangle slots follow those of the instances before it; the
+    tiles go out longest first, ties in (instance, leaf) order."""
+    import numpy as np
+    inst, tiles, first = [], [], 0
+    for b, m in enumerate(sizes):
+        P = max(1, -(-m // L))
+        inst.append([offsets[b], m, ldas[b], L, P, first, first * tri])
+        tiles += [(max(0, min(L, m - i * L)), b, i) for i in range(P)]
+        first += P
+    order = sorted(range(len(tiles)), key=lambda k: -tiles[k][0])      # sorted() is stable
+    return (np.array(inst, dtype=np.int64).reshape(-1, 7),
+            np.array([[tiles[k][1], tiles[k][2]] for k in order], dtype=np.int64).reshape(-1, 2))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_plan_schedule_is_bit_exact(ph, dtype):
+    """The tile table and the per-instance table of a plan, read back from the
+    library, equal an independent enumeration from their definition, entry
+    for entry, on the ragged batch of the batched workload (4096 instances,
+    heights log-uniform in [64, 65536]) with an lda above m and gaps between
+    the instances."""
+    import numpy as np
+    from paper_1002_4250_amd import inputs
+    sizes = [int(v) for v in inputs.batched_sizes()]
+    n = 50
+    ldas = [m + 7 for m in sizes]
+    offsets, off = [], 0
+    for m, ld in zip(sizes, ldas):
+        offsets.append(off)
+        off += ld * n + 13
+    dt = tsqr.TSQR_F64 if dtype == "f64" else tsqr.TSQR_F32
+    arr = lambda v: (ctypes.c_int64 * len(v))(*v)
+    plan = ctypes.c_void_p()
+    st = tsqr.lib().tsqr_batch_plan_create(ph, len(sizes), n, arr(sizes), arr(offsets), arr(ldas), dt,
+                                           ctypes.byref(plan))
+    assert st == 0
+    try:
+        tiles, leaves, L = tsqr.tsqr_batch_plan_info(plan.value)
+        inst, sched = tsqr.tsqr_batch_plan_schedule(plan.value, len(sizes))
+        want_inst, want_sched = _expected_schedule(sizes, offsets, ldas, L, n * (n + 1) // 2)
+        assert leaves == want_inst[:, 4].sum() and tiles == len(want_sched)
+        assert np.array_equal(inst, want_inst)
+        assert np.array_equal(sched, want_sched)
+    finally:
+        tsqr.tsqr_batch_plan_destroy(plan.value)
+    assert tsqr.lib().tsqr_batch_plan_schedule(None, None, None) == -1
+
+
 def test_batch_plan_argument_checks(ph):
     import numpy as np
     L = tsqr.lib()
