@@ -240,6 +240,22 @@ def time_q(torch, tsqr, Ad, steps, warmup, library=True):
     orth32 = float(torch.linalg.norm(Q32.double().t() @ Q32.double()
                                      - torch.eye(n, dtype=torch.float64, device="cuda")).item()) / n ** 0.5
     del A32, ws32, Q32, R32
+    # Q^T B without forming Q: the factorization keeping its reflectors, then
+    # the replay on one right-hand side and on 50
+    del Q
+    torch.cuda.empty_cache()
+    fz = tsqr.Factorization(Ad, h=h)
+    ms_geqrf = timed(lambda: tsqr.Factorization(Ad, h=h), max(1, k // 4), 2)
+    b1 = Ad[:, :1].contiguous()
+    c1 = torch.empty((1, n), dtype=Ad.dtype, device="cuda").t()
+    ms_qt1 = timed(lambda: fz.apply_qt(b1, C=c1), k, min(warmup, 10))
+    c50 = torch.empty((n, n), dtype=Ad.dtype, device="cuda").t()
+    ms_qt50 = timed(lambda: fz.apply_qt(Ad, C=c50), k, min(warmup, 10))
+    qt_err = float(((c50 - fz.R).norm() / fz.R.norm()).item())      # Q^T A = R
+    del fz, b1, c1, c50
+    torch.cuda.empty_cache()
+    log(f"q: geqrf (reflectors kept) {ms_geqrf:.3f} ms; apply Q^T to 1 column {ms_qt1:.3f} ms, "
+        f"to 50 columns {ms_qt50:.3f} ms (Q^T A vs R: {qt_err:.1e})")
     flops = 4.0 * m * n * n        # factorization 2mn^2 + forming Q 2mn^2 (LAPACK's counts for m >> n)
     gbs_min = 16.0 * m * n / (ms_q * 1e-3) / 1e9
     log(f"q: fp32 {ms_q32:.3f} ms per QR with Q, orthogonality {orth32:.1e}")
@@ -255,6 +271,10 @@ def time_q(torch, tsqr, Ad, steps, warmup, library=True):
         "torch_linalg_qr_reduced_ms": lib_ms, "torch_linalg_qr_r_ms": lib_r_ms,
         "fp32": {"value": 1000.0 / ms_q32, "unit": "instances/s", "ms_per_step": ms_q32,
                  "achieved_TFLOPs_4mn2": flops / (ms_q32 * 1e-3) / 1e12, "orthogonality": orth32},
+        "apply_qt": {"what": "tsqr_geqrf_f64 (R and the reflectors) then tsqr_apply_qt_f64 = Q^T B without "
+                             "forming Q", "geqrf_ms": ms_geqrf, "k1_ms": ms_qt1, "k50_ms": ms_qt50,
+                     "k50_achieved_TFLOPs_2mn2k_equiv": 2.0 * m * n * n / (ms_qt50 * 1e-3) / 1e12,
+                     "QtA_vs_R_relF": qt_err},
     }
 
 

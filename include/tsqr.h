@@ -268,6 +268,34 @@ int tsqr_geqr_qr_f64(tsqr_handle_t handle, int64_t m, int64_t n, const double *A
 int tsqr_geqr_qr_f32(tsqr_handle_t handle, int64_t m, int64_t n, const float *A, int64_t lda, float *Q,
                      int64_t ldq, float *R, int64_t ldr, void *ws, int64_t ws_bytes, void *stream);
 
+/* Applying Q^T without forming Q (section 3: Q stays implicit in the leaves'
+ * and the tree's reflectors).  tsqr_geqrf_* is the factorization of
+ * tsqr_geqr_qr_* alone: it returns R (bit-identical to tsqr_geqr_r's with the
+ * same leaf size) and leaves every reflector in ws; argument codes -1 handle,
+ * -2 m, -3 n (n > m is illegal), -4 A, -5 lda, -6 R, -7 ldr, -8 ws,
+ * -9 ws_bytes.  tsqr_apply_qt_* then computes C = Q^T B (n x k, column-major,
+ * ldc >= n) for any B (m x k, column-major, ldb >= m), k >= 0, by replaying
+ * those reflectors on B in the factorization's order: each leaf maps its rows
+ * of B chunk by chunk into an n x k block, the tree's merges combine the
+ * blocks level by level from the leaves up, and the root's sign flips finish
+ * it.  It must follow a tsqr_geqrf_* call of the same precision with the same
+ * handle, m, n and ws, whose contents it reads and does not change, so any
+ * number of right-hand sides can follow one factorization (tsqr_geqr_qr_*
+ * overwrites part of that state while forming Q).  ws is sized by
+ * tsqr_qr_workspace_bytes, which includes the per-leaf blocks for k.  k is
+ * taken in panels of 48 columns in FP64, 64 in FP32 (a separate kernel for
+ * k <= 4).  Asynchronous on `stream`, no allocation.  Argument codes -1
+ * handle, -2 m, -3 n, -4 k, -5 B, -6 ldb, -7 C, -8 ldc, -9 ws, -10 ws_bytes;
+ * TSQR_ERR_UNSUPPORTED for n > TSQR_MAX_N. */
+int tsqr_geqrf_f64(tsqr_handle_t handle, int64_t m, int64_t n, const double *A, int64_t lda, double *R, int64_t ldr,
+                   void *ws, int64_t ws_bytes, void *stream);
+int tsqr_geqrf_f32(tsqr_handle_t handle, int64_t m, int64_t n, const float *A, int64_t lda, float *R, int64_t ldr,
+                   void *ws, int64_t ws_bytes, void *stream);
+int tsqr_apply_qt_f64(tsqr_handle_t handle, int64_t m, int64_t n, int64_t k, const double *B, int64_t ldb, double *C,
+                      int64_t ldc, void *ws, int64_t ws_bytes, void *stream);
+int tsqr_apply_qt_f32(tsqr_handle_t handle, int64_t m, int64_t n, int64_t k, const float *B, int64_t ldb, float *C,
+                      int64_t ldc, void *ws, int64_t ws_bytes, void *stream);
+
 /* ---- mixed precision: FP32 TSQR, then one FP64 correction -------------------
  *
  * For `batch` matrices of equal shape m x n stored in FP32 (instance b at

@@ -990,7 +990,7 @@ struct QrLayout {
     Geometry g;
     int64_t nchunks;         // chunks over all of A (leaf sizes are whole chunks)
     int64_t ldv;             // rows of V: every row of every chunk
-    int64_t off_v, off_tau_leaf, off_vn, off_tau_node, off_qblk, ws_bytes;
+    int64_t off_v, off_tau_leaf, off_vn, off_tau_node, off_qblk, off_tq, ws_bytes;
     int levels;
 };
 
@@ -1014,6 +1014,8 @@ int qr_plan(const tsqr_handle_s* h, int64_t m, int64_t n, int dtype, QrLayout* L
     off += align_up(P * nc * w, kAlign);
     L->off_qblk = off;
     off += align_up(P * nc * nc * w, kAlign);
+    L->off_tq = off;     // the per-leaf n x 64 blocks of tsqr_apply_qt_*
+    off += align_up(P * nc * tsqr::kQtCols * w, kAlign);
     L->ws_bytes = off;
     int levels = 0;
     while (((int64_t)1 << levels) < P) ++levels;
@@ -1021,6 +1023,8 @@ int qr_plan(const tsqr_handle_s* h, int64_t m, int64_t n, int dtype, QrLayout* L
     return 0;
 }
 
+// The factorization with reflector storage alone (Q == nullptr: tsqr_geqrf_*),
+// or followed by the passes that form Q.
 template <typename T>
 hipError_t dispatch_qr(const tsqr::LeafTreeArgs<T>& a, int nc, T* Q, int64_t ldq, int levels, hipStream_t s)
 {
@@ -1031,6 +1035,7 @@ hipError_t dispatch_qr(const tsqr::LeafTreeArgs<T>& a, int nc, T* Q, int64_t ldq
             const auto& at = reinterpret_cast<const tsqr::LeafTreeArgs<tsqr::tag>&>(a);                  \
             tsqr::tag* Qt = reinterpret_cast<tsqr::tag*>(Q);                                             \
             e = tsqr::launch_qr_leaf_tree_##tag##_##NC##_##RPL(at, s);                                   \
+            if (!Qt) return e;                                                                           \
             for (int lv = levels - 1; lv >= 0 && e == hipSuccess; --lv) {                                \
                 const int64_t span = (int64_t)1 << lv;                                                   \
                 const int64_t nodes = at.leaves > span ? (at.leaves - 1 - span) / (2 * span) + 1 : 0;    \
@@ -1046,8 +1051,23 @@ hipError_t dispatch_qr(const tsqr::LeafTreeArgs<T>& a, int nc, T* Q, int64_t ldq
 }
 
 template <typename T>
+hipError_t dispatch_qt(const tsqr::QtArgs<T>& x, int nc, int levels, hipStream_t s)
+{
+    hipError_t e = hipErrorInvalidValue;
+#define TSQR_CALL(tag, NC, RPL)                                                                          \
+    if constexpr (sizeof(T) == sizeof(tsqr::tag)) {                                                      \
+        if (nc == NC) return tsqr::launch_qt_##tag##_##NC##_##RPL(                                        \
+            reinterpret_cast<const tsqr::QtArgs<tsqr::tag>&>(x), levels, s);                             \
+    }
+    TSQR_QR_INSTANCES(TSQR_CALL)
+#undef TSQR_CALL
+    return e;
+}
+
+// Q may be null (the factorization only: R and the stored reflectors).
+template <typename T>
 int geqr_qr(tsqr_handle_t handle, int64_t m, int64_t n, const T* A, int64_t lda, T* Q, int64_t ldq, T* R,
-            int64_t ldr, void* ws, int64_t ws_bytes, void* stream)
+            int64_t ldr, void* ws, int64_t ws_bytes, void* stream, bool form_q = true)
 {
     constexpr int dtype = sizeof(T) == 8 ? TSQR_F64 : TSQR_F32;
     if (!handle) return -1;
@@ -1055,8 +1075,8 @@ int geqr_qr(tsqr_handle_t handle, int64_t m, int64_t n, const T* A, int64_t lda,
     if (n < 0 || n > m) return -3;
     if (n > 0 && !A) return -4;
     if (lda < (m > 1 ? m : 1)) return -5;
-    if (n > 0 && !Q) return -6;
-    if (ldq < (m > 1 ? m : 1)) return -7;
+    if (form_q && n > 0 && !Q) return -6;
+    if (form_q && ldq < (m > 1 ? m : 1)) return -7;
     if (n > 0 && !R) return -8;
     if (ldr < (n > 1 ? n : 1)) return -9;
     if (n == 0) return 0;
@@ -1089,7 +1109,58 @@ int geqr_qr(tsqr_handle_t handle, int64_t m, int64_t n, const T* A, int64_t lda,
     a.qs.Vn = reinterpret_cast<T*>(base + L.off_vn);
     a.qs.tau_node = reinterpret_cast<T*>(base + L.off_tau_node);
     a.qs.qblk = reinterpret_cast<T*>(base + L.off_qblk);
-    e = dispatch_qr<T>(a, L.g.nc, Q, ldq, L.levels, s);
+    e = dispatch_qr<T>(a, L.g.nc, form_q ? Q : nullptr, ldq, L.levels, s);
+    return hip_status(handle, e);
+}
+
+template <typename T>
+int apply_qt(tsqr_handle_t handle, int64_t m, int64_t n, int64_t k, const T* B, int64_t ldb, T* C, int64_t ldc,
+             void* ws, int64_t ws_bytes, void* stream)
+{
+    constexpr int dtype = sizeof(T) == 8 ? TSQR_F64 : TSQR_F32;
+    if (!handle) return -1;
+    if (m < 0) return -2;
+    if (n < 0 || n > m) return -3;
+    if (k < 0) return -4;
+    if (n > 0 && k > 0 && !B) return -5;
+    if (ldb < (m > 1 ? m : 1)) return -6;
+    if (n > 0 && k > 0 && !C) return -7;
+    if (ldc < (n > 1 ? n : 1)) return -8;
+    if (n == 0 || k == 0) return 0;
+    if (n > TSQR_MAX_N) return TSQR_ERR_UNSUPPORTED;
+    if (k > INT32_MAX) return TSQR_ERR_UNSUPPORTED;
+    QrLayout L;
+    int rc = qr_plan(handle, m, n, dtype, &L);
+    if (rc) return rc;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) != 0) return -9;
+    if (ws_bytes < L.ws_bytes) return -10;
+    if (handle->planning_only) return TSQR_ERR_NO_DEVICE;
+    char* base = static_cast<char*>(ws);
+    tsqr::QtArgs<T> x;
+    tsqr::LeafTreeArgs<T>& a = x.a;
+    a.A = nullptr;
+    a.m = m;
+    a.lda = m > 1 ? m : 1;
+    a.n = (int)n;
+    a.leaf_rows = L.g.leaf_rows;
+    a.leaves = (int)L.g.leaves;
+    a.tri = nullptr;
+    a.tickets = nullptr;
+    a.R = nullptr;
+    a.ldr = 0;
+    a.qs.V = reinterpret_cast<T*>(base + L.off_v);
+    a.qs.ldv = L.ldv;
+    a.qs.tau_leaf = reinterpret_cast<T*>(base + L.off_tau_leaf);
+    a.qs.Vn = reinterpret_cast<T*>(base + L.off_vn);
+    a.qs.tau_node = reinterpret_cast<T*>(base + L.off_tau_node);
+    a.qs.qblk = reinterpret_cast<T*>(base + L.off_qblk);
+    x.B = B;
+    x.ldb = ldb;
+    x.k = (int)k;
+    x.tq = reinterpret_cast<T*>(base + L.off_tq);
+    x.C = C;
+    x.ldc = ldc;
+    const hipError_t e = dispatch_qt<T>(x, L.g.nc, L.levels, static_cast<hipStream_t>(stream));
     return hip_status(handle, e);
 }
 }  // namespace
@@ -1118,6 +1189,32 @@ int tsqr_geqr_qr_f32(tsqr_handle_t handle, int64_t m, int64_t n, const float* A,
                      int64_t ldq, float* R, int64_t ldr, void* ws, int64_t ws_bytes, void* stream)
 {
     return geqr_qr<float>(handle, m, n, A, lda, Q, ldq, R, ldr, ws, ws_bytes, stream);
+}
+
+int tsqr_geqrf_f64(tsqr_handle_t handle, int64_t m, int64_t n, const double* A, int64_t lda, double* R, int64_t ldr,
+                   void* ws, int64_t ws_bytes, void* stream)
+{
+    const int rc = geqr_qr<double>(handle, m, n, A, lda, nullptr, m > 1 ? m : 1, R, ldr, ws, ws_bytes, stream, false);
+    return rc <= -8 ? rc + 2 : rc;
+}
+
+int tsqr_geqrf_f32(tsqr_handle_t handle, int64_t m, int64_t n, const float* A, int64_t lda, float* R, int64_t ldr,
+                   void* ws, int64_t ws_bytes, void* stream)
+{
+    const int rc = geqr_qr<float>(handle, m, n, A, lda, nullptr, m > 1 ? m : 1, R, ldr, ws, ws_bytes, stream, false);
+    return rc <= -8 ? rc + 2 : rc;
+}
+
+int tsqr_apply_qt_f64(tsqr_handle_t handle, int64_t m, int64_t n, int64_t k, const double* B, int64_t ldb, double* C,
+                      int64_t ldc, void* ws, int64_t ws_bytes, void* stream)
+{
+    return apply_qt<double>(handle, m, n, k, B, ldb, C, ldc, ws, ws_bytes, stream);
+}
+
+int tsqr_apply_qt_f32(tsqr_handle_t handle, int64_t m, int64_t n, int64_t k, const float* B, int64_t ldb, float* C,
+                      int64_t ldc, void* ws, int64_t ws_bytes, void* stream)
+{
+    return apply_qt<float>(handle, m, n, k, B, ldb, C, ldc, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -90,6 +90,45 @@ hipError_t TSQR_QR_FN2(q_leaf, TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL)(const
                        dim3(dev::kWave), 0, s, a, Q, ldq);
     return hipGetLastError();
 }
+// C = Q^T B for one panel of k <= 64 columns: leaf pass, the tree levels
+// leaves first, the sign fix
+template <int KS>
+static hipError_t launch_qt_panel(const QtArgs<TSQR_INST_TAG>& x, int levels, hipStream_t s)
+{
+    hipLaunchKernelGGL((dev::qt_leaf_kernel<TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL, KS>), dim3(x.a.leaves),
+                       dim3(dev::kWave), 0, s, x);
+    hipError_t e = hipGetLastError();
+    for (int lv = 0; lv < levels && e == hipSuccess; ++lv) {
+        const int64_t span = (int64_t)1 << lv;
+        const int64_t nodes = x.a.leaves > span ? (x.a.leaves - 1 - span) / (2 * span) + 1 : 0;
+        if (nodes <= 0) continue;
+        hipLaunchKernelGGL((dev::qt_tree_kernel<TSQR_INST_TAG, TSQR_INST_NC, KS>), dim3((unsigned)nodes),
+                           dim3(dev::kWave), 0, s, x, lv);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
+    const int cells = x.a.n * x.k;
+    hipLaunchKernelGGL((dev::qt_finish_kernel<TSQR_INST_TAG, TSQR_INST_NC>),
+                       dim3((unsigned)((cells + dev::kWave - 1) / dev::kWave)), dim3(dev::kWave), 0, s, x);
+    return hipGetLastError();
+}
+hipError_t TSQR_QR_FN2(qt, TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL)(const QtArgs<TSQR_INST_TAG>& x, int levels,
+                                                                    hipStream_t s)
+{
+    // panels of 48 columns in FP64 (12 slots of 8 rows stay in registers with
+    // the step's working set), 64 in FP32; one slot for k <= 4
+    constexpr int KW = sizeof(TSQR_INST_TAG) == 8 ? 12 : 16;
+    if (x.k <= 4) return x.k > 0 ? launch_qt_panel<1>(x, levels, s) : hipSuccess;
+    hipError_t e = hipSuccess;
+    for (int k0 = 0; k0 < x.k && e == hipSuccess; k0 += 4 * KW) {
+        QtArgs<TSQR_INST_TAG> xp = x;
+        xp.B = x.B + (int64_t)k0 * x.ldb;
+        xp.C = x.C + (int64_t)k0 * x.ldc;
+        xp.k = x.k - k0 < 4 * KW ? x.k - k0 : 4 * KW;
+        e = launch_qt_panel<KW>(xp, levels, s);
+    }
+    return e;
+}
 #elif defined(TSQR_INST_OP)
 #define TSQR_OP_FN(tag, nc) launch_qr_uppers_##tag##_##nc
 #define TSQR_OP_FN2(tag, nc) TSQR_OP_FN(tag, nc)

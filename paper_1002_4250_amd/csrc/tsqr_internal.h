@@ -113,6 +113,21 @@ struct SampleArgs {
 hipError_t launch_mixed_sample(const SampleArgs& a, int batch, hipStream_t s);
 hipError_t launch_fill_u32(unsigned* p, int64_t count, unsigned value, hipStream_t s);
 
+// Applying Q^T from the stored reflectors: B (m x k, column-major, ldb), the
+// per-leaf NC x kQtCols blocks tq (column-major, ld NC), the output C (n x k,
+// ldc).
+constexpr int kQtCols = 64;
+template <typename T>
+struct QtArgs {
+    LeafTreeArgs<T> a;
+    const T* B;
+    int64_t ldb;
+    int k;
+    T* tq;
+    T* C;
+    int64_t ldc;
+};
+
 // Q-factor mode (FP64): the leaf+tree kernel storing its reflectors, one
 // launch per tree level top-down, then one pass over the leaves.
 #define TSQR_QR_INSTANCES_DECL(tag, NC, RPL)                                                          \
@@ -120,7 +135,8 @@ hipError_t launch_fill_u32(unsigned* p, int64_t count, unsigned value, hipStream
     hipError_t launch_q_tree_##tag##_##NC##_##RPL(const LeafTreeArgs<tag>& a, int level, int nodes,   \
                                                    hipStream_t s);                                    \
     hipError_t launch_q_leaf_##tag##_##NC##_##RPL(const LeafTreeArgs<tag>& a, tag* Q, int64_t ldq,    \
-                                                   hipStream_t s);
+                                                   hipStream_t s);                                    \
+    hipError_t launch_qt_##tag##_##NC##_##RPL(const QtArgs<tag>& x, int levels, hipStream_t s);
 TSQR_QR_INSTANCES(TSQR_QR_INSTANCES_DECL)
 #undef TSQR_QR_INSTANCES_DECL
 

@@ -57,6 +57,10 @@ SIGNATURES = [
     ("tsqr_qr_workspace_bytes", _i64, [_p, _i64, _i64, _i]),
     ("tsqr_geqr_qr_f64", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
     ("tsqr_geqr_qr_f32", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
+    ("tsqr_geqrf_f64", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
+    ("tsqr_geqrf_f32", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
+    ("tsqr_apply_qt_f64", _i, [_p, _i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
+    ("tsqr_apply_qt_f32", _i, [_p, _i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
     ("tsqr_mixed_plan_create", _i, [_p, _i64, _i64, _i64, _i64, _i64, ctypes.POINTER(_p)]),
     ("tsqr_mixed_plan_destroy", _i, [_p]),
     ("tsqr_mixed_workspace_bytes", _i64, [_p]),
@@ -532,6 +536,52 @@ def tsqr_geqr_qr_f64(handle, m, n, A, lda, Q, ldq, R, ldr, ws, ws_bytes, stream)
 
 def tsqr_geqr_qr_f32(handle, m, n, A, lda, Q, ldq, R, ldr, ws, ws_bytes, stream) -> int:
     return lib().tsqr_geqr_qr_f32(handle, m, n, A, lda, Q, ldq, R, ldr, ws, ws_bytes, stream)
+
+
+class Factorization:
+    """The factorization with its reflectors kept (``tsqr_geqrf_*``): ``R``,
+    and ``apply_qt(B)`` = Q^T B for any device matrix B with m rows, without
+    forming Q.  Holds the workspace the reflectors live in."""
+
+    def __init__(self, A, h=None):
+        import torch
+        if A.dtype not in (torch.float64, torch.float32):
+            raise TypeError("A must be float64 or float32")
+        if not A.is_cuda:
+            raise ValueError("A must be a device tensor")
+        self.torch = torch
+        self.m, self.n, lda = _col_major(A)
+        self.dtype, self.dev = A.dtype, A.device
+        self.h = h or handle(self.dev.index or 0)
+        code = TSQR_F64 if A.dtype == torch.float64 else TSQR_F32
+        self.ws = torch.empty(max(tsqr_qr_workspace_bytes(self.h, self.m, self.n, code), 256), dtype=torch.uint8,
+                              device=self.dev)
+        self.R = torch.empty((self.n, self.n), dtype=A.dtype, device=self.dev).t()
+        fn = lib().tsqr_geqrf_f64 if A.dtype == torch.float64 else lib().tsqr_geqrf_f32
+        st = fn(self.h, self.m, self.n, A.data_ptr(), lda, self.R.data_ptr(), max(self.n, 1), self.ws.data_ptr(),
+                _ws_bytes(self.ws, self.dev), _stream_ptr(torch, self.dev))
+        _check("tsqr_geqrf", st, self.h)
+
+    def apply_qt(self, B, C=None):
+        """C = Q^T B (n x k, column-major) for B (m x k, column-major) or a
+        vector of length m (then C is a vector of length n)."""
+        torch = self.torch
+        vec = B.dim() == 1
+        if vec:
+            B = B.reshape(-1, 1)
+        if B.dtype != self.dtype or B.device != self.dev:
+            raise ValueError("B must match the factored matrix's dtype and device")
+        mb, k, ldb = _col_major(B)
+        if mb != self.m:
+            raise ValueError(f"B has {mb} rows, the factored matrix {self.m}")
+        if C is None:
+            C = torch.empty((k, self.n), dtype=self.dtype, device=self.dev).t()
+        ldc = _check_matrix(C, "C", self.n, k, self.dtype, self.dev)
+        fn = lib().tsqr_apply_qt_f64 if self.dtype == torch.float64 else lib().tsqr_apply_qt_f32
+        st = fn(self.h, self.m, self.n, k, B.data_ptr(), ldb, C.data_ptr(), ldc, self.ws.data_ptr(),
+                _ws_bytes(self.ws, self.dev), _stream_ptr(torch, self.dev))
+        _check("tsqr_apply_qt", st, self.h)
+        return C.reshape(-1) if vec else C
 
 
 def geqr_qr(A, Q=None, R=None, ws=None, h=None):

@@ -359,6 +359,43 @@ def test_qr_workspace_query(ph):
     assert tsqr.tsqr_qr_workspace_bytes(ph, m, n, F32) < tsqr.tsqr_qr_workspace_bytes(ph, m, n, F64)
 
 
+def test_geqrf_and_apply_qt_argument_checks(ph):
+    L = tsqr.lib()
+    F64, F32 = tsqr.TSQR_F64, tsqr.TSQR_F32
+    m, n = 100000, 50
+    for code, geqrf, apply in ((F64, L.tsqr_geqrf_f64, L.tsqr_apply_qt_f64),
+                               (F32, L.tsqr_geqrf_f32, L.tsqr_apply_qt_f32)):
+        need = tsqr.tsqr_qr_workspace_bytes(ph, m, n, code)
+        # the workspace also holds one n x 64 block per leaf for apply_qt
+        leaves = tsqr.tsqr_plan_info(ph, m, n, code)[1]
+        assert need >= leaves * n * 64 * (8 if code == F64 else 4)
+        assert geqrf(None, m, n, 1, m, 1, n, 256, need, None) == -1
+        assert geqrf(ph, -1, n, 1, m, 1, n, 256, need, None) == -2
+        assert geqrf(ph, m, m + 1, 1, m, 1, n, 256, need, None) == -3
+        assert geqrf(ph, m, n, None, m, 1, n, 256, need, None) == -4
+        assert geqrf(ph, m, n, 1, m - 1, 1, n, 256, need, None) == -5
+        assert geqrf(ph, m, n, 1, m, None, n, 256, need, None) == -6
+        assert geqrf(ph, m, n, 1, m, 1, n - 1, 256, need, None) == -7
+        assert geqrf(ph, m, n, 1, m, 1, n, None, need, None) == -8
+        assert geqrf(ph, m, n, 1, m, 1, n, 256, need - 1, None) == -9
+        assert geqrf(ph, m, n, 1, m, 1, n, 256, need, None) == tsqr.TSQR_ERR_NO_DEVICE
+        k = 3
+        assert apply(None, m, n, k, 1, m, 1, n, 256, need, None) == -1
+        assert apply(ph, -1, n, k, 1, m, 1, n, 256, need, None) == -2
+        assert apply(ph, m, m + 1, k, 1, m, 1, n, 256, need, None) == -3
+        assert apply(ph, m, n, -1, 1, m, 1, n, 256, need, None) == -4
+        assert apply(ph, m, n, k, None, m, 1, n, 256, need, None) == -5
+        assert apply(ph, m, n, k, 1, m - 1, 1, n, 256, need, None) == -6
+        assert apply(ph, m, n, k, 1, m, None, n, 256, need, None) == -7
+        assert apply(ph, m, n, k, 1, m, 1, n - 1, 256, need, None) == -8
+        assert apply(ph, m, n, k, 1, m, 1, n, None, need, None) == -9
+        assert apply(ph, m, n, k, 1, m, 1, n, 256, need - 1, None) == -10
+        assert apply(ph, m, n, k, 1, m, 1, n, 256, need, None) == tsqr.TSQR_ERR_NO_DEVICE
+        # nothing to do: no checks of the pointers, no device needed
+        assert apply(ph, m, n, 0, None, m, None, n, None, 0, None) == 0
+        assert apply(ph, m, 65, k, 1, m, 1, 65, 256, need, None) == tsqr.TSQR_ERR_UNSUPPORTED
+
+
 def test_tuning_table_steers_the_automatic_policy(ph):
     F64, F32 = tsqr.TSQR_F64, tsqr.TSQR_F32
     base = {m: tsqr.tsqr_plan_info(ph, m, 50, F64) for m in (1 << 16, 1 << 18, 1 << 20, 1 << 21)}

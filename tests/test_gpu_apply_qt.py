@@ -1,0 +1,110 @@
+"""Q^T B without forming Q (tsqr_geqrf_* then tsqr_apply_qt_*).
+
+For A of full column rank, Q with R's diagonal positive is unique: Q = A R^-1.
+The reference is the oracle's Q (that definition evaluated on the CPU in FP64
+with the oracle's R) times B, at 1e-12 relative (Frobenius) for the
+well-conditioned inputs here; the defining identities are checked beside it:
+Q^T A = R, and the least-squares solution R^-1 Q^T b equals LAPACK's.  R from
+the factorization-only call must equal, bit for bit, the R of the call that
+forms Q (the same kernel and leaf size).  At the full size (2^22 x 50) the
+identities Q^T A = R and Q^T (A x) = R x are checked.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+from paper_1002_4250_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1002_4250_amd import tsqr  # noqa: E402
+
+
+def relF(X, Y):
+    return float(np.linalg.norm(X - Y) / max(np.linalg.norm(Y), 1e-300))
+
+
+def to_dev(A, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(A.T)).to(dtype).cuda().t()
+
+
+@pytest.mark.parametrize("m,n,k,leaf_rows", [(256, 50, 1, 0), (256, 50, 7, 128), (5000, 17, 4, 0),
+                                             (5000, 17, 5, 256), (70000, 50, 3, 0), (70000, 50, 48, 1000),
+                                             (50, 50, 2, 0), (4097, 64, 49, 384), (1000, 1, 1, 0),
+                                             (9000, 32, 100, 128), (20000, 50, 64, 0)])
+def test_apply_qt_matches_definition(m, n, k, leaf_rows):
+    A = inputs.uniform(m, n, 41 + n)
+    B = inputs.uniform(m, k, 43 + k)
+    h = tsqr.handle(0)
+    tsqr.tsqr_set_option(h, tsqr.TSQR_OPT_LEAF_ROWS, leaf_rows)
+    try:
+        Ad = to_dev(A)
+        f = tsqr.Factorization(Ad)
+        C = f.apply_qt(to_dev(B)).cpu().numpy()
+        C2 = f.apply_qt(to_dev(B)).cpu().numpy()      # the stored state is read, not changed
+        QtA = f.apply_qt(Ad).cpu().numpy()
+        R = f.R.cpu().numpy()
+        _, Rq = tsqr.geqr_qr(Ad)
+        torch.cuda.synchronize()
+        Rq = Rq.cpu().numpy()
+    finally:
+        tsqr.tsqr_set_option(h, tsqr.TSQR_OPT_LEAF_ROWS, 0)
+    assert np.array_equal(R, Rq)
+    assert np.array_equal(C, C2)
+    Q = oracle.q_factor(A)
+    assert relF(C, Q.T @ B) < 1e-12, relF(C, Q.T @ B)
+    assert relF(QtA, R) < 1e-13, relF(QtA, R)
+    assert np.all(np.isfinite(C))
+
+
+def test_least_squares_from_apply_qt():
+    """x = R^-1 Q^T b minimizes ||A x - b||: it equals LAPACK's least-squares
+    solution (gelsd), for a b with a residual, at a few right-hand sides."""
+    m, n = 30000, 50
+    A = inputs.uniform(m, n, 51)
+    b = inputs.uniform(m, 3, 52)
+    f = tsqr.Factorization(to_dev(A))
+    c = f.apply_qt(to_dev(b)).cpu().numpy()
+    R = f.R.cpu().numpy()
+    x = scipy.linalg.solve_triangular(R, c)
+    x_ref = np.linalg.lstsq(A, b, rcond=None)[0]
+    assert relF(x, x_ref) < 1e-12, relF(x, x_ref)
+    # a single vector goes through the vector form
+    cv = f.apply_qt(to_dev(b[:, :1]).reshape(-1)).cpu().numpy()
+    assert np.array_equal(cv, c[:, 0])
+
+
+def test_apply_qt_fp32():
+    """FP32 against the FP64 definition on the FP32-rounded inputs, at the
+    FP32 gate of the R factor (1e-5)."""
+    m, n, k = 20000, 50, 5
+    A = inputs.uniform(m, n, 61).astype(np.float32)
+    B = inputs.uniform(m, k, 62).astype(np.float32)
+    f = tsqr.Factorization(to_dev(A, torch.float32))
+    C = f.apply_qt(to_dev(B, torch.float32)).cpu().numpy().astype(np.float64)
+    Q = oracle.q_factor(A.astype(np.float64))
+    assert relF(C, Q.T @ B.astype(np.float64)) < 1e-5
+
+
+def test_apply_qt_full_size_identities():
+    """2^22 x 50, the benchmark's matrix: Q^T A = R (every entry) and
+    Q^T (A x) = R x for random x, two identities of Q = A R^-1."""
+    m, n = 1 << 22, 50
+    A = inputs.uniform(m, n, 1)
+    Ad = to_dev(A)
+    f = tsqr.Factorization(Ad)
+    X = inputs.uniform(n, 4, 71)
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).cuda().t()
+    AX = (Ad @ Xd).t().contiguous().t()
+    QtA = f.apply_qt(Ad).cpu().numpy()
+    QtAX = f.apply_qt(AX).cpu().numpy()
+    R = f.R.cpu().numpy()
+    torch.cuda.synchronize()
+    assert relF(QtA, R) < 1e-13, relF(QtA, R)
+    assert relF(QtAX, R @ X) < 1e-12, relF(QtAX, R @ X)
+    assert relF(R, oracle.r_factor(A)) < 1e-10
