@@ -477,7 +477,7 @@ def time_mixed(torch, tsqr, inputs, steps, warmup, batch=256, m=1 << 16, n=50):
         "speedup_vs_plain_fp64": ms_64 / ms_mixed,
         "achieved_TFLOPs_2mn2": flops / (ms_mixed * 1e-3) / 1e12,
         "sampled_rtilde": {
-            "what": f"R~ from the fp32 TSQR of a stratified sample of {sample_rows} rows (16-row blocks, "
+            "what": f"R~ from the fp32 TSQR of a stratified sample of {sample_rows} rows (64-row blocks, "
                     "seed 1), then the same fp64 correction over all of A",
             "value": batch / (ms_sampled * 1e-3), "unit": "instances/s", "ms_per_step": ms_sampled,
             "fallbacks_to_fp64": fallbacks_s, "speedup_vs_plain_fp64": ms_64 / ms_sampled},

@@ -331,9 +331,9 @@ int tsqr_mixed_exec(tsqr_mixed_plan_t plan, const float *A, double *R, int64_t l
 /* The same plan with R~ computed from a row sample instead of all of A (the
  * sampled preconditioner: the paper's method is unchanged in the fallback,
  * only the preconditioner of the FP64 pass is cheaper).  The sample has
- * sample_rows rows rounded up to a multiple of 16: the m rows are cut into
- * sample_rows/16 strata of equal length (to within one row), and from each a
- * block of 16 contiguous rows at a uniform offset is taken, the offsets drawn
+ * sample_rows rows rounded up to a multiple of 64: the m rows are cut into
+ * sample_rows/64 strata of equal length (to within one row), and from each a
+ * block of 64 contiguous rows at a uniform offset is taken, the offsets drawn
  * from SplitMix64 (Steele, Lea and Flood 2014) of (seed, instance, stratum),
  * so a plan always takes the same sample.  The FP32 TSQR then factors the
  * sample, and the FP64 pass over all of A corrects as above: the result is

@@ -781,15 +781,15 @@ int gram_width(int nc)
 
 namespace {
 // Both creators: sample_rows = 0 factors all of A in FP32, otherwise a sample
-// of that many rows (rounded up to a multiple of 16; all of A when that
-// reaches m).
+// of that many rows (rounded up to a multiple of the 64-row sample block; all
+// of A when that reaches m).
 int mixed_plan_make(tsqr_handle_t h, int64_t batch, int64_t m, int64_t n, int64_t lda, int64_t stride_a,
                     int64_t sample_rows, uint64_t seed, tsqr_mixed_plan_t* out)
 {
     if (n > TSQR_MAX_N) return TSQR_ERR_UNSUPPORTED;
     const int nc = n > 0 ? padded_columns(n) : 16;
     if (nc < 0) return TSQR_ERR_UNSUPPORTED;
-    int64_t srows = (sample_rows + 15) / 16 * 16;
+    int64_t srows = (sample_rows + tsqr::kSampleBlock - 1) / tsqr::kSampleBlock * tsqr::kSampleBlock;
     if (srows >= m) srows = 0;
     // the FP32 factorization runs over A itself, or over the sample buffer
     // (instance b's s x n sample at b*s*n in it, ld s)

@@ -125,7 +125,7 @@ hipError_t TSQR_QR_FN2(qt, TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL)(const QtA
         xp.B = x.B + (int64_t)k0 * x.ldb;
         xp.C = x.C + (int64_t)k0 * x.ldc;
         xp.k = x.k - k0 < 4 * KW ? x.k - k0 : 4 * KW;
-        e = launch_qt_panel<KW>(xp, levels, s);
+        e = xp.k <= 4 ? launch_qt_panel<1>(xp, levels, s) : launch_qt_panel<KW>(xp, levels, s);
     }
     return e;
 }
@@ -183,30 +183,30 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x)
 }
 
 // Workgroup (k, b) copies block k of instance b's sample: stratum k holds rows
-// [k q + min(k, r), ...) of length q + [k < r] (m = nb q + r, nb = s/16), and
-// the block starts at a uniform offset in [0, length - 16] drawn from
-// splitmix64 of (seed, b, k).  Lane t copies row t % 16 of the block in
-// columns t/16, t/16 + 4, ...
+// [k q + min(k, r), ...) of length q + [k < r] (m = nb q + r, nb = s/64), and
+// the block of 64 rows starts at a uniform offset in [0, length - 64] drawn
+// from splitmix64 of (seed, b, k).  Lane t copies row t of the block, one
+// column after another (each wavefront load is 256 contiguous bytes).
 __global__ void __launch_bounds__(64) mixed_sample_kernel(SampleArgs a)
 {
-    const int64_t nb = a.s / 16, k = blockIdx.x;
+    const int64_t nb = a.s / kSampleBlock, k = blockIdx.x;
     const int b = blockIdx.y;
     const int64_t q = a.m / nb, r = a.m % nb;
     const int64_t lo = k * q + (k < r ? k : r);
     const int64_t len = q + (k < r ? 1 : 0);
     const uint64_t h = splitmix64(a.seed ^ ((uint64_t)b << 32) ^ (uint64_t)k);
-    const int64_t start = lo + (int64_t)(h % (uint64_t)(len - 15));
+    const int64_t start = lo + (int64_t)(h % (uint64_t)(len - kSampleBlock + 1));
     const int t = threadIdx.x;
-    const float* src = a.A + (int64_t)b * a.stride_a + start + (t & 15);
-    float* dst = a.S + (int64_t)b * a.s * a.n + 16 * k + (t & 15);
-    for (int c = t >> 4; c < a.n; c += 4) dst[(int64_t)c * a.s] = src[(int64_t)c * a.lda];
+    const float* src = a.A + (int64_t)b * a.stride_a + start + t;
+    float* dst = a.S + (int64_t)b * a.s * a.n + kSampleBlock * k + t;
+    for (int c = 0; c < a.n; ++c) dst[(int64_t)c * a.s] = src[(int64_t)c * a.lda];
 }
 }  // namespace dev
 
 hipError_t launch_mixed_sample(const SampleArgs& a, int batch, hipStream_t s)
 {
     if (batch <= 0 || a.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(dev::mixed_sample_kernel, dim3((unsigned)(a.s / 16), batch), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(dev::mixed_sample_kernel, dim3((unsigned)(a.s / kSampleBlock), batch), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

@@ -98,10 +98,12 @@ TSQR_DECLARE_BATCH_IN32(64)
 
 hipError_t launch_zero_u32(unsigned* p, int64_t count, hipStream_t s);
 
-// Row sample of every instance for the sampled preconditioner: rows blocks of
-// 16 contiguous rows, one block drawn uniformly inside each of s/16 equal
-// strata of the m rows, copied to S (instance b's s x n sample at S + b*s*n,
-// column-major, ld s).  s is a multiple of 16 with 16 <= s < m.
+// Row sample of every instance for the sampled preconditioner: blocks of
+// kSampleBlock contiguous rows, one block drawn uniformly inside each of
+// s/kSampleBlock equal strata of the m rows, copied to S (instance b's s x n
+// sample at S + b*s*n, column-major, ld s).  s is a multiple of kSampleBlock
+// with kSampleBlock <= s < m.
+constexpr int kSampleBlock = 64;
 struct SampleArgs {
     const float* A;
     int64_t m, lda, stride_a;
