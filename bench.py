@@ -451,6 +451,7 @@ def time_mixed(torch, tsqr, inputs, steps, warmup, batch=256, m=1 << 16, n=50):
     Rts = ms_.rtilde().cpu().numpy()
     fallbacks_s = int(flags_s.sum().item())
     del ms_, Rs_d
+    learned = [learned_vs_sampled(torch, tsqr, Ad, batch, m, n, s_, timed, k, min(warmup, 3)) for s_ in (256, 4096)]
     sizes = np.full(batch, m, dtype=np.int64)
     offsets = np.arange(batch, dtype=np.int64) * m * n
     p32 = tsqr.BatchPlan(sizes, offsets, n, torch.float32)
@@ -481,7 +482,66 @@ def time_mixed(torch, tsqr, inputs, steps, warmup, batch=256, m=1 << 16, n=50):
                     "seed 1), then the same fp64 correction over all of A",
             "value": batch / (ms_sampled * 1e-3), "unit": "instances/s", "ms_per_step": ms_sampled,
             "fallbacks_to_fp64": fallbacks_s, "speedup_vs_plain_fp64": ms_64 / ms_sampled},
+        "learned_rtilde": learned,
     }, (flat, kappas, Rm, R32, Rtm, Rs, Rts)
+
+
+def learned_vs_sampled(torch, tsqr, Ad, batch, m, n, sample_rows, timed, k, w):
+    """The learned correction of the sampled R~ against the un-learned one
+    with the same sample: an MLP on features of R~ (library kernels, BF16
+    matrix cores), trained here on 16 generated batches of the same shape
+    (G diag(sigma) V^T with Gaussian G, a different family from the
+    evaluation batch's orthonormal U), then run on the evaluation batch."""
+    import numpy as np
+    from paper_1002_4250_amd import surrogate
+    plan = tsqr.MixedPlan(batch, m, n, sample_rows=sample_rows, seed=1)
+    t = time.perf_counter()
+    data = surrogate.gather(plan, 16, seed=1000)
+    model = surrogate.Mlp(2 * n - 1, n, H=256, seed=1)
+    steps = 600
+    losses = surrogate.train(model, data, steps, minibatch=128, lr=1e-3, seed=2)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t
+    del data
+    R0 = torch.empty((batch, n, n), dtype=torch.float64, device="cuda")
+    R1 = torch.empty_like(R0)
+    f0 = torch.zeros(batch, dtype=torch.int32, device="cuda")
+    f1 = torch.zeros_like(f0)
+    ms_plain = timed(lambda: plan.launch(Ad, R0, f0), k, w)
+    last = [None]
+
+    def run_learned():
+        last[0] = surrogate.learned_launch(model, plan, Ad, R1, f1)
+
+    ms_learned = timed(run_learned, k, w)
+    torch.cuda.synchronize()
+    # the targets of the evaluation batch: how far the network's row factors
+    # are from the ones the R of A asks for, against no correction
+    ev = surrogate.Dataset(surrogate.features(plan.rtilde(), batch, n).reshape(2 * n - 1, batch),
+                           surrogate.targets(R0, plan.rtilde(), batch, n).reshape(n, batch))
+    mse_model, mse_zero = surrogate.predict_mse(model, ev)
+    R, Rt0, Rt1 = R0.cpu().numpy(), plan.rtilde().cpu().numpy(), last[-1].cpu().numpy()
+    k0 = np.array([np.linalg.cond(R[b].T @ np.linalg.inv(np.triu(Rt0[b].T.astype(np.float64))))
+                   for b in range(batch)])
+    k1 = np.array([np.linalg.cond(R[b].T @ np.linalg.inv(np.triu(Rt1[b].T.astype(np.float64))))
+                   for b in range(batch)])
+    fb0, fb1 = int(f0.sum().item()), int(f1.sum().item())
+    log(f"learned R~ (sample {sample_rows}): trained in {t_train:.1f} s (loss {losses[-1]:.2e}); "
+        f"kappa(A R~^-1) median {np.median(k0):.3f} -> {np.median(k1):.3f}, max {k0.max():.3f} -> {k1.max():.3f}; "
+        f"{ms_plain:.2f} -> {ms_learned:.2f} ms; fallbacks {fb0} -> {fb1}")
+    del plan
+    return {
+        "sample_rows": sample_rows,
+        "training": {"instances": 16 * batch, "steps": steps, "minibatch": 128, "seconds": t_train,
+                     "final_loss": losses[-1]},
+        "target_mse_eval_batch": {"learned": mse_model, "zero_correction": mse_zero},
+        "kappa_A_Rtilde_inv": {"unlearned_median": float(np.median(k0)), "learned_median": float(np.median(k1)),
+                               "unlearned_max": float(k0.max()), "learned_max": float(k1.max()),
+                               "learned_lower_fraction": float(np.mean(k1 < k0))},
+        "fallbacks_to_fp64": {"unlearned": fb0, "learned": fb1},
+        "instances_per_s": {"unlearned": batch / (ms_plain * 1e-3), "learned": batch / (ms_learned * 1e-3)},
+        "ms_per_step": {"unlearned": ms_plain, "learned": ms_learned},
+    }
 
 
 def mixed_accuracy(oracle, np, data, m=1 << 16, n=50, picks=(0, 64, 128, 160, 192, 224, 255)):

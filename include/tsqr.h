@@ -345,10 +345,75 @@ int tsqr_mixed_exec(tsqr_mixed_plan_t plan, const float *A, double *R, int64_t l
 int tsqr_mixed_plan_create_sampled(tsqr_handle_t handle, int64_t batch, int64_t m, int64_t n, int64_t lda,
                                    int64_t stride_a, int64_t sample_rows, uint64_t seed, tsqr_mixed_plan_t *plan);
 
+/* The correction with the caller's R~ (device, FP32, instance b's n x n upper
+ * triangle at Rt + b*n*n, column-major, ld n) instead of the plan's own FP32
+ * factorization (e.g. a learned correction of the sampled R~, below): the
+ * FP64 pass, the guards and the fallback are those of tsqr_mixed_exec, so the
+ * result is the R of A whatever R~ is.  Argument codes as tsqr_mixed_exec's
+ * with -3 for Rt and the later ones one lower (-4 R, -5 ldr, -7 ws, -8
+ * ws_bytes). */
+int tsqr_mixed_exec_rtilde(tsqr_mixed_plan_t plan, const float *A, const float *Rt, double *R, int64_t ldr,
+                           int *fallback, void *ws, int64_t ws_bytes, void *stream);
+
+/* Only the first stage of tsqr_mixed_exec: R~ by the FP32 TSQR of A (or of its
+ * row sample, for a sampled plan), left in the workspace at
+ * tsqr_mixed_rtilde_offset (e.g. as the input of a learned correction, whose
+ * result then goes to tsqr_mixed_exec_rtilde).  Nothing is written for m = 0.
+ * Argument codes: -1 plan, -2 A, -3 ws (NULL or not 256-byte aligned), -4
+ * ws_bytes; TSQR_ERR_NO_DEVICE on a planning handle. */
+int tsqr_mixed_rtilde_exec(tsqr_mixed_plan_t plan, const float *A, void *ws, int64_t ws_bytes, void *stream);
+
 /* Byte offset in the workspace of R~ after tsqr_mixed_exec: FP32, instance b's
  * n x n upper triangle at offset + 4*b*n*n, column-major, ld n (for
  * diagnostics such as the conditioning of A R~^-1); -1 for a NULL plan. */
 int64_t tsqr_mixed_rtilde_offset(tsqr_mixed_plan_t plan);
+
+/* ---- the learned correction of the sampled preconditioner -------------------
+ *
+ * The slot where a model can enter without changing the result is R~ (above):
+ * these calls are the building blocks of a small MLP that maps features of a
+ * sampled R~ to a correction of it, trained on the GPU.  All arrays are device
+ * FP32, column-major with the given leading dimension; every call is
+ * asynchronous on `stream` and allocates nothing.  Argument codes: -k for the
+ * k-th argument; TSQR_ERR_NO_DEVICE on a planning handle.
+ *
+ * tsqr_gemm_bf16: C (M x N, ldc) = alpha op(A) op(B) + beta C with op(X) = X or
+ *   X^T (ta, tb nonzero: stored transposed; op(A) is M x K, op(B) K x N).  A
+ *   and B are rounded to BF16 as they are loaded (round to nearest even), the
+ *   products accumulate in FP32 on the BF16 matrix cores (the 16x16x16 BF16
+ *   instruction); beta = 0 does not read C.
+ * tsqr_mlp_bias_act: Z (rows x cols, ld) := act(Z + bias), bias per column, act
+ *   ReLU if relu is nonzero, else the identity.
+ * tsqr_mlp_relu_grad: dA := dA where out > 0, else 0 (out: the ReLU output).
+ * tsqr_mlp_colsum: s(j) = sum over the rows of Z(:, j), in row order.
+ * tsqr_mlp_mse: D = 2 (Y - T)/(rows cols) and *loss = sum (Y - T)^2/(rows cols)
+ *   (loss: one device float), in a fixed order.
+ * tsqr_mlp_adam: one Adam step (Kingma and Ba 2015) on count parameters, step
+ *   >= 1 for the bias corrections.
+ * tsqr_surrogate_features: for a batch of R~ (instance b at Rt + b*n*n, ld n),
+ *   X (batch x (2n - 1), ld batch): log|R~(i,i)| minus its mean over i, then
+ *   R~(i-1, i)/|R~(i-1, i-1)| for i = 1..n-1.
+ * tsqr_surrogate_targets: Y (batch x n, ld batch) = log(|R(i,i)|/|R~(i,i)|)
+ *   minus its mean over i, R the FP64 R of all of A (instance b at R + b*ldr*n).
+ * tsqr_surrogate_apply: Rout = R~ with row i scaled by exp(Y(b, i)), Y(b, i)
+ *   clamped to [-1, 1] (a NaN to -1): no row changes by more than a factor e. */
+int tsqr_gemm_bf16(tsqr_handle_t handle, int ta, int tb, int64_t M, int64_t N, int64_t K, float alpha, const float *A,
+                   int64_t lda, const float *B, int64_t ldb, float beta, float *C, int64_t ldc, void *stream);
+int tsqr_mlp_bias_act(tsqr_handle_t handle, float *Z, int64_t rows, int64_t cols, int64_t ld, const float *bias,
+                      int relu, void *stream);
+int tsqr_mlp_relu_grad(tsqr_handle_t handle, float *dA, const float *out, int64_t rows, int64_t cols, int64_t ld,
+                       void *stream);
+int tsqr_mlp_colsum(tsqr_handle_t handle, const float *Z, int64_t rows, int64_t cols, int64_t ld, float *s,
+                    void *stream);
+int tsqr_mlp_mse(tsqr_handle_t handle, const float *Y, const float *T, float *D, int64_t rows, int64_t cols,
+                 int64_t ld, float *loss, void *stream);
+int tsqr_mlp_adam(tsqr_handle_t handle, float *p, const float *g, float *m, float *v, int64_t count, float lr,
+                  float b1, float b2, float eps, int64_t step, void *stream);
+int tsqr_surrogate_features(tsqr_handle_t handle, const float *Rt, int64_t batch, int64_t n, float *X, void *stream);
+int tsqr_surrogate_targets(tsqr_handle_t handle, const double *R, int64_t ldr, const float *Rt, int64_t batch,
+                           int64_t n, float *Y, void *stream);
+int tsqr_surrogate_apply(tsqr_handle_t handle, const float *Rt, const float *Y, int64_t batch, int64_t n, float *Rout,
+                         void *stream);
 
 #ifdef __cplusplus
 }

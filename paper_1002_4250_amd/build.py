@@ -50,7 +50,8 @@ def instances():
     return units
 
 
-KERNEL_DEPS = ["tsqr_inst.hip", "tsqr_device.h", "tsqr_mixed.h", "tsqr_q.h", "tsqr_internal.h", "tsqr_instances.h"]
+KERNEL_DEPS = ["tsqr_inst.hip", "tsqr_device.h", "tsqr_mixed.h", "tsqr_q.h", "tsqr_internal.h", "tsqr_instances.h",
+               "tsqr_mlp.h"]
 API_DEPS = ["tsqr_api.cpp", "tsqr_internal.h", "tsqr_instances.h", "tsqr_mixed.h", "tsqr_device.h"]
 
 

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <new>
 #include <string.h>
@@ -907,8 +908,66 @@ int64_t tsqr_mixed_workspace_bytes(tsqr_mixed_plan_t plan)
     return plan->ws_bytes;
 }
 
+namespace {
+int mixed_exec(tsqr_mixed_plan_t plan, const float* A, const float* Rt_in, double* R, int64_t ldr, int* fallback,
+               void* ws, int64_t ws_bytes, void* stream);
+int rtilde_stage(tsqr_mixed_plan_t plan, const float* A, char* base, void* stream);
+}
+
 int tsqr_mixed_exec(tsqr_mixed_plan_t plan, const float* A, double* R, int64_t ldr, int* fallback, void* ws,
                     int64_t ws_bytes, void* stream)
+{
+    return mixed_exec(plan, A, nullptr, R, ldr, fallback, ws, ws_bytes, stream);
+}
+
+int tsqr_mixed_exec_rtilde(tsqr_mixed_plan_t plan, const float* A, const float* Rt, double* R, int64_t ldr,
+                           int* fallback, void* ws, int64_t ws_bytes, void* stream)
+{
+    if (plan && plan->batch > 0 && plan->n > 0 && plan->m > 0 && !Rt) return -3;
+    const int rc = mixed_exec(plan, A, Rt, R, ldr, fallback, ws, ws_bytes, stream);
+    // argument codes shift by one past A (the R~ argument is -3)
+    return rc <= -3 ? rc - 1 : rc;
+}
+
+int tsqr_mixed_rtilde_exec(tsqr_mixed_plan_t plan, const float* A, void* ws, int64_t ws_bytes, void* stream)
+{
+    if (!plan) return -1;
+    const bool work = plan->batch > 0 && plan->n > 0 && plan->m > 0;
+    if (work && !A) return -2;
+    if (!work) return 0;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) != 0) return -3;
+    if (ws_bytes < plan->ws_bytes) return -4;
+    if (plan->h->planning_only) return TSQR_ERR_NO_DEVICE;
+    return rtilde_stage(plan, A, static_cast<char*>(ws), stream);
+}
+
+namespace {
+// The first stage: R~ of A (or of its row sample) by the FP32 batched TSQR,
+// into the plan's R~ area of the workspace at base
+int rtilde_stage(tsqr_mixed_plan_t plan, const float* A, char* base, void* stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float* Rt = reinterpret_cast<float*>(base + plan->off_rt);
+    const float* src = A;
+    if (plan->sample_rows) {
+        tsqr::SampleArgs sa;
+        sa.A = A;
+        sa.m = plan->m;
+        sa.lda = plan->lda;
+        sa.stride_a = plan->stride_a;
+        sa.n = (int)plan->n;
+        sa.S = reinterpret_cast<float*>(base + plan->off_sample);
+        sa.s = plan->sample_rows;
+        sa.seed = plan->seed;
+        hipError_t e = tsqr::launch_mixed_sample(sa, (int)plan->batch, s);
+        if (e != hipSuccess) return hip_status(plan->h, e);
+        src = sa.S;
+    }
+    return tsqr_batch_exec(plan->inner, src, Rt, plan->n, base + plan->off_inner, plan->inner_bytes, stream);
+}
+
+int mixed_exec(tsqr_mixed_plan_t plan, const float* A, const float* Rt_in, double* R, int64_t ldr, int* fallback,
+               void* ws, int64_t ws_bytes, void* stream)
 {
     if (!plan) return -1;
     const bool work = plan->batch > 0 && plan->n > 0;
@@ -922,24 +981,8 @@ int tsqr_mixed_exec(tsqr_mixed_plan_t plan, const float* A, double* R, int64_t l
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(ws);
     float* Rt = reinterpret_cast<float*>(base + plan->off_rt);
-    int rc = 0;
-    if (plan->m > 0) {
-        const float* src = A;
-        if (plan->sample_rows) {
-            tsqr::SampleArgs sa;
-            sa.A = A;
-            sa.m = plan->m;
-            sa.lda = plan->lda;
-            sa.stride_a = plan->stride_a;
-            sa.n = (int)plan->n;
-            sa.S = reinterpret_cast<float*>(base + plan->off_sample);
-            sa.s = plan->sample_rows;
-            sa.seed = plan->seed;
-            hipError_t e = tsqr::launch_mixed_sample(sa, (int)plan->batch, s);
-            if (e != hipSuccess) return hip_status(plan->h, e);
-            src = sa.S;
-        }
-        rc = tsqr_batch_exec(plan->inner, src, Rt, plan->n, base + plan->off_inner, plan->inner_bytes, stream);
+    if (plan->m > 0 && !Rt_in) {
+        const int rc = rtilde_stage(plan, A, base, stream);
         if (rc) return rc;
     }
     tsqr::MixedArgs a;
@@ -948,7 +991,7 @@ int tsqr_mixed_exec(tsqr_mixed_plan_t plan, const float* A, double* R, int64_t l
     a.lda = plan->lda;
     a.stride_a = plan->stride_a;
     a.n = (int)plan->n;
-    a.Rt = Rt;
+    a.Rt = Rt_in ? Rt_in : Rt;     // the caller's R~ (tsqr_mixed_exec_rtilde), else the one just computed
     a.part = reinterpret_cast<double*>(base + plan->off_part);
     a.rows_per_block = plan->rows_per_block;
     a.blocks = plan->blocks;
@@ -979,6 +1022,7 @@ int tsqr_mixed_exec(tsqr_mixed_plan_t plan, const float* A, double* R, int64_t l
         e = tsqr::launch_fill_u32(reinterpret_cast<unsigned*>(fallback), plan->batch, 1u, s);
     return hip_status(plan->h, e);
 }
+}  // namespace
 
 // ---- the Q factor ------------------------------------------------------------
 
@@ -1215,6 +1259,159 @@ int tsqr_apply_qt_f32(tsqr_handle_t handle, int64_t m, int64_t n, int64_t k, con
                       int64_t ldc, void* ws, int64_t ws_bytes, void* stream)
 {
     return apply_qt<float>(handle, m, n, k, B, ldb, C, ldc, ws, ws_bytes, stream);
+}
+
+// ---- the learned correction of the sampled preconditioner -----------------------
+
+namespace {
+int kernel_status(tsqr_handle_t h, hipError_t e) { return hip_status(h, e); }
+bool dims_ok(int64_t v) { return v >= 0 && v <= INT32_MAX; }
+}  // namespace
+
+int tsqr_gemm_bf16(tsqr_handle_t h, int ta, int tb, int64_t M, int64_t N, int64_t K, float alpha, const float* A,
+                   int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc, void* stream)
+{
+    if (!h) return -1;
+    if (!dims_ok(M)) return -4;
+    if (!dims_ok(N)) return -5;
+    if (!dims_ok(K)) return -6;
+    const int64_t arows = ta ? K : M, brows = tb ? N : K;
+    if (M > 0 && N > 0 && K > 0 && !A) return -8;
+    if (lda < (arows > 1 ? arows : 1)) return -9;
+    if (M > 0 && N > 0 && K > 0 && !B) return -10;
+    if (ldb < (brows > 1 ? brows : 1)) return -11;
+    if (M > 0 && N > 0 && !C) return -13;
+    if (ldc < (M > 1 ? M : 1)) return -14;
+    if (M == 0 || N == 0) return 0;
+    if (h->planning_only) return TSQR_ERR_NO_DEVICE;
+    tsqr::GemmArgs g;
+    g.ta = ta ? 1 : 0;
+    g.tb = tb ? 1 : 0;
+    g.M = (int)M;
+    g.N = (int)N;
+    g.K = (int)K;
+    g.alpha = alpha;
+    g.beta = beta;
+    g.A = A;
+    g.lda = lda;
+    g.B = B;
+    g.ldb = ldb;
+    g.C = C;
+    g.ldc = ldc;
+    return kernel_status(h, tsqr::launch_gemm_bf16(g, static_cast<hipStream_t>(stream)));
+}
+
+int tsqr_mlp_bias_act(tsqr_handle_t h, float* Z, int64_t rows, int64_t cols, int64_t ld, const float* bias, int relu,
+                      void* stream)
+{
+    if (!h) return -1;
+    if (!dims_ok(rows)) return -3;
+    if (!dims_ok(cols)) return -4;
+    if (rows > 0 && cols > 0 && (!Z || !bias)) return !Z ? -2 : -6;
+    if (ld < (rows > 1 ? rows : 1)) return -5;
+    if (rows == 0 || cols == 0) return 0;
+    if (h->planning_only) return TSQR_ERR_NO_DEVICE;
+    return kernel_status(h, tsqr::launch_bias_act(Z, (int)rows, (int)cols, ld, bias, relu ? 1 : 0,
+                                                  static_cast<hipStream_t>(stream)));
+}
+
+int tsqr_mlp_relu_grad(tsqr_handle_t h, float* dA, const float* out, int64_t rows, int64_t cols, int64_t ld,
+                       void* stream)
+{
+    if (!h) return -1;
+    if (!dims_ok(rows)) return -4;
+    if (!dims_ok(cols)) return -5;
+    if (rows > 0 && cols > 0 && (!dA || !out)) return !dA ? -2 : -3;
+    if (ld < (rows > 1 ? rows : 1)) return -6;
+    if (rows == 0 || cols == 0) return 0;
+    if (h->planning_only) return TSQR_ERR_NO_DEVICE;
+    return kernel_status(h, tsqr::launch_relu_grad(dA, out, (int)rows, (int)cols, ld, static_cast<hipStream_t>(stream)));
+}
+
+int tsqr_mlp_colsum(tsqr_handle_t h, const float* Z, int64_t rows, int64_t cols, int64_t ld, float* s, void* stream)
+{
+    if (!h) return -1;
+    if (!dims_ok(rows)) return -3;
+    if (!dims_ok(cols)) return -4;
+    if (cols > 0 && ((rows > 0 && !Z) || !s)) return !s ? -6 : -2;
+    if (ld < (rows > 1 ? rows : 1)) return -5;
+    if (cols == 0) return 0;
+    if (h->planning_only) return TSQR_ERR_NO_DEVICE;
+    return kernel_status(h, tsqr::launch_colsum(Z, (int)rows, (int)cols, ld, s, static_cast<hipStream_t>(stream)));
+}
+
+int tsqr_mlp_mse(tsqr_handle_t h, const float* Y, const float* T, float* D, int64_t rows, int64_t cols, int64_t ld,
+                 float* loss, void* stream)
+{
+    if (!h) return -1;
+    if (!dims_ok(rows) || rows == 0) return -5;
+    if (!dims_ok(cols) || cols == 0) return -6;
+    if (!Y) return -2;
+    if (!T) return -3;
+    if (!D) return -4;
+    if (ld < rows) return -7;
+    if (!loss) return -8;
+    if (h->planning_only) return TSQR_ERR_NO_DEVICE;
+    return kernel_status(h, tsqr::launch_mse(Y, T, D, (int)rows, (int)cols, ld, loss, static_cast<hipStream_t>(stream)));
+}
+
+int tsqr_mlp_adam(tsqr_handle_t h, float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1,
+                  float b2, float eps, int64_t step, void* stream)
+{
+    if (!h) return -1;
+    if (count < 0) return -6;
+    if (count > 0 && (!p || !g || !m || !v)) return !p ? -2 : (!g ? -3 : (!m ? -4 : -5));
+    if (step < 1) return -11;
+    if (count == 0) return 0;
+    if (h->planning_only) return TSQR_ERR_NO_DEVICE;
+    // the bias corrections in FP64 (1 - b2^t loses most of its bits in FP32)
+    const float c1 = (float)(1.0 - std::pow((double)b1, (double)step));
+    const float c2 = (float)(1.0 - std::pow((double)b2, (double)step));
+    return kernel_status(h, tsqr::launch_adam(p, g, m, v, count, lr, b1, b2, eps, c1, c2,
+                                              static_cast<hipStream_t>(stream)));
+}
+
+int tsqr_surrogate_features(tsqr_handle_t h, const float* Rt, int64_t batch, int64_t n, float* X, void* stream)
+{
+    if (!h) return -1;
+    if (!dims_ok(batch)) return -3;
+    if (n < 1 || n > TSQR_MAX_N) return -4;
+    if (batch > 0 && !Rt) return -2;
+    if (batch > 0 && !X) return -5;
+    if (batch == 0) return 0;
+    if (h->planning_only) return TSQR_ERR_NO_DEVICE;
+    return kernel_status(h, tsqr::launch_surrogate_features(Rt, (int)batch, (int)n, X, static_cast<hipStream_t>(stream)));
+}
+
+int tsqr_surrogate_targets(tsqr_handle_t h, const double* R, int64_t ldr, const float* Rt, int64_t batch, int64_t n,
+                           float* Y, void* stream)
+{
+    if (!h) return -1;
+    if (!dims_ok(batch)) return -5;
+    if (n < 1 || n > TSQR_MAX_N) return -6;
+    if (batch > 0 && !R) return -2;
+    if (ldr < n) return -3;
+    if (batch > 0 && !Rt) return -4;
+    if (batch > 0 && !Y) return -7;
+    if (batch == 0) return 0;
+    if (h->planning_only) return TSQR_ERR_NO_DEVICE;
+    return kernel_status(h, tsqr::launch_surrogate_targets(R, ldr, Rt, (int)batch, (int)n, Y,
+                                                           static_cast<hipStream_t>(stream)));
+}
+
+int tsqr_surrogate_apply(tsqr_handle_t h, const float* Rt, const float* Y, int64_t batch, int64_t n, float* Rout,
+                         void* stream)
+{
+    if (!h) return -1;
+    if (!dims_ok(batch)) return -4;
+    if (n < 1 || n > TSQR_MAX_N) return -5;
+    if (batch > 0 && !Rt) return -2;
+    if (batch > 0 && !Y) return -3;
+    if (batch > 0 && !Rout) return -6;
+    if (batch == 0) return 0;
+    if (h->planning_only) return TSQR_ERR_NO_DEVICE;
+    return kernel_status(h, tsqr::launch_surrogate_apply(Rt, Y, (int)batch, (int)n, Rout,
+                                                         static_cast<hipStream_t>(stream)));
 }
 
 }  // extern "C"

@@ -8,6 +8,9 @@
 #include "tsqr_internal.h"
 #include "tsqr_mixed.h"
 #include "tsqr_q.h"
+#if defined(TSQR_INST_COMMON)
+#include "tsqr_mlp.h"  // non-template kernels: defined in this unit only
+#endif
 
 
 namespace tsqr {
@@ -202,6 +205,70 @@ __global__ void __launch_bounds__(64) mixed_sample_kernel(SampleArgs a)
     for (int c = 0; c < a.n; ++c) dst[(int64_t)c * a.s] = src[(int64_t)c * a.lda];
 }
 }  // namespace dev
+
+namespace {
+unsigned grid_for(int64_t count, int block)
+{
+    const int64_t g = (count + block - 1) / block;
+    return (unsigned)(g < 4096 ? (g > 0 ? g : 1) : 4096);
+}
+}  // namespace
+
+hipError_t launch_gemm_bf16(const GemmArgs& g, hipStream_t s)
+{
+    if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dev::gemm_bf16_kernel, dim3((unsigned)((g.M + 15) / 16), (unsigned)((g.N + 15) / 16)),
+                       dim3(dev::kWave), 0, s, g);
+    return hipGetLastError();
+}
+hipError_t launch_bias_act(float* Z, int rows, int cols, int64_t ld, const float* bias, int relu, hipStream_t s)
+{
+    hipLaunchKernelGGL(dev::bias_act_kernel, dim3(grid_for((int64_t)rows * cols, 256)), dim3(256), 0, s, Z, rows, cols,
+                       ld, bias, relu);
+    return hipGetLastError();
+}
+hipError_t launch_relu_grad(float* dA, const float* out, int rows, int cols, int64_t ld, hipStream_t s)
+{
+    hipLaunchKernelGGL(dev::relu_grad_kernel, dim3(grid_for((int64_t)rows * cols, 256)), dim3(256), 0, s, dA, out,
+                       rows, cols, ld);
+    return hipGetLastError();
+}
+hipError_t launch_colsum(const float* Z, int rows, int cols, int64_t ld, float* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(dev::colsum_kernel, dim3(grid_for(cols, 64)), dim3(64), 0, s, Z, rows, cols, ld, out);
+    return hipGetLastError();
+}
+hipError_t launch_mse(const float* Y, const float* T, float* D, int rows, int cols, int64_t ld, float* loss,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL(dev::mse_kernel, dim3(1), dim3(256), 0, s, Y, T, D, rows, cols, ld, loss);
+    return hipGetLastError();
+}
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1, float b2,
+                       float eps, float c1, float c2, hipStream_t s)
+{
+    hipLaunchKernelGGL(dev::adam_kernel, dim3(grid_for(count, 256)), dim3(256), 0, s, p, g, m, v, count, lr, b1, b2,
+                       eps, c1, c2);
+    return hipGetLastError();
+}
+hipError_t launch_surrogate_features(const float* Rt, int batch, int n, float* X, hipStream_t s)
+{
+    hipLaunchKernelGGL(dev::surrogate_features_kernel, dim3(grid_for(batch, 64)), dim3(64), 0, s, Rt, batch, n, X);
+    return hipGetLastError();
+}
+hipError_t launch_surrogate_targets(const double* R, int64_t ldr, const float* Rt, int batch, int n, float* Y,
+                                    hipStream_t s)
+{
+    hipLaunchKernelGGL(dev::surrogate_targets_kernel, dim3(grid_for(batch, 64)), dim3(64), 0, s, R, ldr, Rt, batch,
+                       n, Y);
+    return hipGetLastError();
+}
+hipError_t launch_surrogate_apply(const float* Rt, const float* Y, int batch, int n, float* Rout, hipStream_t s)
+{
+    hipLaunchKernelGGL(dev::surrogate_apply_kernel, dim3(grid_for((int64_t)batch * n * n, 256)), dim3(256), 0, s, Rt,
+                       Y, batch, n, Rout);
+    return hipGetLastError();
+}
 
 hipError_t launch_mixed_sample(const SampleArgs& a, int batch, hipStream_t s)
 {

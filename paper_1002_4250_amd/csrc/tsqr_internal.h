@@ -113,6 +113,31 @@ struct SampleArgs {
     uint64_t seed;
 };
 hipError_t launch_mixed_sample(const SampleArgs& a, int batch, hipStream_t s);
+
+// The learned correction of the sampled preconditioner (tsqr_mlp.h).
+struct GemmArgs {
+    int ta, tb;
+    int M, N, K;
+    float alpha, beta;
+    const float* A;
+    int64_t lda;
+    const float* B;
+    int64_t ldb;
+    float* C;
+    int64_t ldc;
+};
+hipError_t launch_gemm_bf16(const GemmArgs& g, hipStream_t s);
+hipError_t launch_bias_act(float* Z, int rows, int cols, int64_t ld, const float* bias, int relu, hipStream_t s);
+hipError_t launch_relu_grad(float* dA, const float* out, int rows, int cols, int64_t ld, hipStream_t s);
+hipError_t launch_colsum(const float* Z, int rows, int cols, int64_t ld, float* out, hipStream_t s);
+hipError_t launch_mse(const float* Y, const float* T, float* D, int rows, int cols, int64_t ld, float* loss,
+                      hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1, float b2,
+                       float eps, float c1, float c2, hipStream_t s);
+hipError_t launch_surrogate_features(const float* Rt, int batch, int n, float* X, hipStream_t s);
+hipError_t launch_surrogate_targets(const double* R, int64_t ldr, const float* Rt, int batch, int n, float* Y,
+                                    hipStream_t s);
+hipError_t launch_surrogate_apply(const float* Rt, const float* Y, int batch, int n, float* Rout, hipStream_t s);
 hipError_t launch_fill_u32(unsigned* p, int64_t count, unsigned value, hipStream_t s);
 
 // Applying Q^T from the stored reflectors: B (m x k, column-major, ldb), the

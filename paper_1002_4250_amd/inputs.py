@@ -137,3 +137,28 @@ def conditioned_batch(batch: int, m: int, n: int, log10_kappa_max: float = 8.0, 
         A = conditioned(m, n, float(kappas[i]), seed=[seed, i], dtype=dtype)
         flat[i * m * n:(i + 1) * m * n] = A.T.ravel()
     return flat, kappas
+
+
+def conditioned_batch_device(torch, batch: int, m: int, n: int, log10_kappa_max: float = 8.0, seed: int = 0,
+                             device="cuda"):
+    """A device-side counterpart of :func:`conditioned_batch` for large
+    training sets: A_i = G_i diag(sigma_i) V_i^T with G_i (m x n) standard
+    normal draws from a device generator seeded with ``seed`` (so cond_2(A_i)
+    is kappa_i times cond_2(G_i), about 1 + 2 sqrt(n/m)), V_i the orthonormal
+    factor of CPU normal draws from a generator seeded with ``seed``, sigma_j =
+    kappa_i^(-j/(n-1)) and kappa_i = 10^(log10_kappa_max i/(batch-1)), formed
+    in FP32.  Returns (flat FP32 device tensor, instance i column-major at
+    i*m*n; kappas as a numpy array)."""
+    kappas = 10.0 ** (log10_kappa_max * np.arange(batch) / max(batch - 1, 1))
+    gc = torch.Generator(device="cpu")
+    gc.manual_seed(int(seed))
+    V, _ = torch.linalg.qr(torch.randn((batch, n, n), generator=gc, dtype=torch.float64))
+    sig = torch.from_numpy(kappas[:, None] ** (-np.arange(n)[None, :] / max(n - 1, 1)))
+    Vs = (V * sig[:, None, :]).to(device=device, dtype=torch.float32)
+    gd = torch.Generator(device=device)
+    gd.manual_seed(int(seed))
+    Gt = torch.randn((batch, n, m), generator=gd, device=device, dtype=torch.float32)
+    # row c of instance i's A^T = V diag(sigma) G^T is column c of A_i
+    At = torch.bmm(Vs, Gt)
+    del Gt
+    return At.reshape(-1), kappas

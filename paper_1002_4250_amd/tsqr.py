@@ -68,6 +68,19 @@ SIGNATURES = [
     ("tsqr_batch_plan_schedule", _i, [_p, _p, _p]),
     ("tsqr_mixed_plan_create_sampled", _i, [_p, _i64, _i64, _i64, _i64, _i64, _i64, ctypes.c_uint64, ctypes.POINTER(_p)]),
     ("tsqr_mixed_rtilde_offset", _i64, [_p]),
+    ("tsqr_mixed_exec_rtilde", _i, [_p, _p, _p, _p, _i64, _p, _p, _i64, _p]),
+    ("tsqr_mixed_rtilde_exec", _i, [_p, _p, _p, _i64, _p]),
+    ("tsqr_gemm_bf16", _i, [_p, _i, _i, _i64, _i64, _i64, ctypes.c_float, _p, _i64, _p, _i64, ctypes.c_float, _p,
+                            _i64, _p]),
+    ("tsqr_mlp_bias_act", _i, [_p, _p, _i64, _i64, _i64, _p, _i, _p]),
+    ("tsqr_mlp_relu_grad", _i, [_p, _p, _p, _i64, _i64, _i64, _p]),
+    ("tsqr_mlp_colsum", _i, [_p, _p, _i64, _i64, _i64, _p, _p]),
+    ("tsqr_mlp_mse", _i, [_p, _p, _p, _p, _i64, _i64, _i64, _p, _p]),
+    ("tsqr_mlp_adam", _i, [_p, _p, _p, _p, _p, _i64, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                           _i64, _p]),
+    ("tsqr_surrogate_features", _i, [_p, _p, _i64, _i64, _p, _p]),
+    ("tsqr_surrogate_targets", _i, [_p, _p, _i64, _p, _i64, _i64, _p, _p]),
+    ("tsqr_surrogate_apply", _i, [_p, _p, _p, _i64, _i64, _p, _p]),
 ]
 
 _LOCK = threading.Lock()
@@ -503,6 +516,30 @@ class MixedPlan:
         flags = torch.zeros(max(self.batch, 1), dtype=torch.int32, device=self.dev)
         self.launch(A_flat, R, flags)
         return R, [int(v) for v in flags[:self.batch].cpu().tolist()]
+
+    def launch_rtilde(self, A_flat, Rt, R, flags=None):
+        """The correction with the caller's R~ (a (batch, n, n) float32 device
+        tensor whose [b] is instance b's R~ stored column-major) instead of
+        the plan's own FP32 factorization; otherwise as ``launch``."""
+        torch = self.torch
+        _check_flat(A_flat, "A", self.a_elems, torch.float32, self.dev)
+        _check_flat(Rt, "Rt", self.batch * self.n * self.n, torch.float32, self.dev)
+        _check_flat(R, "R", self.batch * self.n * self.n, torch.float64, self.dev)
+        if flags is not None:
+            _check_flat(flags, "flags", self.batch, torch.int32, self.dev)
+        st = lib().tsqr_mixed_exec_rtilde(self.plan, A_flat.data_ptr(), Rt.data_ptr(), R.data_ptr(), self.n,
+                                          flags.data_ptr() if flags is not None else None, self.ws.data_ptr(),
+                                          self.ws.numel(), _stream_ptr(torch, self.dev))
+        _check("tsqr_mixed_exec_rtilde", st, self.h)
+
+    def launch_first_stage(self, A_flat):
+        """Only the FP32 stage: R~ of A (or of the row sample) into the
+        workspace, read with ``rtilde()``."""
+        torch = self.torch
+        _check_flat(A_flat, "A", self.a_elems, torch.float32, self.dev)
+        st = lib().tsqr_mixed_rtilde_exec(self.plan, A_flat.data_ptr(), self.ws.data_ptr(), self.ws.numel(),
+                                          _stream_ptr(torch, self.dev))
+        _check("tsqr_mixed_rtilde_exec", st, self.h)
 
     def rtilde(self):
         """R~ of the last call, a (batch, n, n) float32 view of the workspace

@@ -535,3 +535,136 @@ def test_noalloc_entry_point_checks_on_the_host(ph):
     assert f(ph, 1 << 22, 50, A, 1 << 22, R, 50, None) == tsqr.TSQR_ERR_SCRATCH
     tsqr.tsqr_set_option(ph, tsqr.TSQR_OPT_LEAF_ROWS, 0)
     assert b"scratch" in L.tsqr_status_string(tsqr.TSQR_ERR_SCRATCH)
+
+
+def test_rtilde_entries_argument_checks(ph):
+    """tsqr_mixed_exec_rtilde (the caller's R~ is argument 3) and
+    tsqr_mixed_rtilde_exec (the FP32 stage alone) on a planning handle."""
+    L = tsqr.lib()
+    p = tsqr.tsqr_mixed_plan_create_sampled(ph, 3, 10000, 50, 10000, 500000, 1024, 5)
+    try:
+        need = tsqr.tsqr_mixed_workspace_bytes(p)
+        buf = ctypes.create_string_buffer(need + 512)
+        ws = (ctypes.addressof(buf) + 255) // 256 * 256
+        f = L.tsqr_mixed_exec_rtilde
+        assert f(None, 1, 1, 1, 50, None, ws, need, None) == -1
+        assert f(p, None, 1, 1, 50, None, ws, need, None) == -2
+        assert f(p, 1, None, 1, 50, None, ws, need, None) == -3
+        assert f(p, 1, 1, None, 50, None, ws, need, None) == -4
+        assert f(p, 1, 1, 1, 49, None, ws, need, None) == -5
+        assert f(p, 1, 1, 1, 50, None, None, need, None) == -7
+        assert f(p, 1, 1, 1, 50, None, ws + 8, need, None) == -7
+        assert f(p, 1, 1, 1, 50, None, ws, need - 1, None) == -8
+        assert f(p, 1, 1, 1, 50, None, ws, need, None) == tsqr.TSQR_ERR_NO_DEVICE
+        g = L.tsqr_mixed_rtilde_exec
+        assert g(None, 1, ws, need, None) == -1
+        assert g(p, None, ws, need, None) == -2
+        assert g(p, 1, None, need, None) == -3
+        assert g(p, 1, ws + 8, need, None) == -3
+        assert g(p, 1, ws, need - 1, None) == -4
+        assert g(p, 1, ws, need, None) == tsqr.TSQR_ERR_NO_DEVICE
+    finally:
+        tsqr.tsqr_mixed_plan_destroy(p)
+    # an empty plan has nothing to do
+    e = tsqr.tsqr_mixed_plan_create(ph, 0, 100, 8, 100, 800)
+    try:
+        assert L.tsqr_mixed_rtilde_exec(e, None, None, 0, None) == 0
+    finally:
+        tsqr.tsqr_mixed_plan_destroy(e)
+
+
+def test_learned_correction_argument_checks(ph):
+    """The MLP and surrogate calls: -k for the k-th argument, empty sizes are
+    no-ops, a planning handle stops before any launch."""
+    L = tsqr.lib()
+    ND = tsqr.TSQR_ERR_NO_DEVICE
+    g = L.tsqr_gemm_bf16
+    assert g(None, 0, 0, 4, 4, 4, 1.0, 1, 4, 1, 4, 0.0, 1, 4, None) == -1
+    assert g(ph, 0, 0, -1, 4, 4, 1.0, 1, 4, 1, 4, 0.0, 1, 4, None) == -4
+    assert g(ph, 0, 0, 4, -1, 4, 1.0, 1, 4, 1, 4, 0.0, 1, 4, None) == -5
+    assert g(ph, 0, 0, 4, 4, -1, 1.0, 1, 4, 1, 4, 0.0, 1, 4, None) == -6
+    assert g(ph, 0, 0, 4, 4, 4, 1.0, None, 4, 1, 4, 0.0, 1, 4, None) == -8
+    assert g(ph, 0, 0, 5, 4, 4, 1.0, 1, 4, 1, 4, 0.0, 1, 5, None) == -9       # lda < M
+    assert g(ph, 1, 0, 4, 4, 5, 1.0, 1, 4, 1, 5, 0.0, 1, 4, None) == -9       # A stored K x M: lda < K
+    assert g(ph, 0, 0, 4, 4, 4, 1.0, 1, 4, None, 4, 0.0, 1, 4, None) == -10
+    assert g(ph, 0, 0, 4, 4, 5, 1.0, 1, 4, 1, 4, 0.0, 1, 4, None) == -11      # ldb < K
+    assert g(ph, 0, 1, 4, 5, 4, 1.0, 1, 4, 1, 4, 0.0, 1, 4, None) == -11      # B stored N x K: ldb < N
+    assert g(ph, 0, 0, 4, 4, 4, 1.0, 1, 4, 1, 4, 0.0, None, 4, None) == -13
+    assert g(ph, 0, 0, 4, 4, 4, 1.0, 1, 4, 1, 4, 0.0, 1, 3, None) == -14
+    assert g(ph, 0, 0, 0, 4, 4, 1.0, None, 1, None, 4, 0.0, None, 1, None) == 0
+    assert g(ph, 0, 0, 4, 4, 4, 1.0, 1, 4, 1, 4, 0.0, 1, 4, None) == ND
+    # K = 0 writes beta C (operands unread)
+    assert g(ph, 0, 0, 4, 4, 0, 1.0, None, 4, None, 1, 0.0, 1, 4, None) == ND
+    b = L.tsqr_mlp_bias_act
+    assert b(None, 1, 4, 4, 4, 1, 1, None) == -1
+    assert b(ph, None, 4, 4, 4, 1, 1, None) == -2
+    assert b(ph, 1, -1, 4, 4, 1, 1, None) == -3
+    assert b(ph, 1, 4, -1, 4, 1, 1, None) == -4
+    assert b(ph, 1, 4, 4, 3, 1, 1, None) == -5
+    assert b(ph, 1, 4, 4, 4, None, 1, None) == -6
+    assert b(ph, None, 0, 4, 1, None, 1, None) == 0
+    assert b(ph, 1, 4, 4, 4, 1, 1, None) == ND
+    r = L.tsqr_mlp_relu_grad
+    assert r(None, 1, 1, 4, 4, 4, None) == -1
+    assert r(ph, None, 1, 4, 4, 4, None) == -2
+    assert r(ph, 1, None, 4, 4, 4, None) == -3
+    assert r(ph, 1, 1, -1, 4, 4, None) == -4
+    assert r(ph, 1, 1, 4, -1, 4, None) == -5
+    assert r(ph, 1, 1, 4, 4, 3, None) == -6
+    assert r(ph, 1, 1, 4, 4, 4, None) == ND
+    c = L.tsqr_mlp_colsum
+    assert c(None, 1, 4, 4, 4, 1, None) == -1
+    assert c(ph, None, 4, 4, 4, 1, None) == -2
+    assert c(ph, 1, -1, 4, 4, 1, None) == -3
+    assert c(ph, 1, 4, -1, 4, 1, None) == -4
+    assert c(ph, 1, 4, 4, 3, 1, None) == -5
+    assert c(ph, 1, 4, 4, 4, None, None) == -6
+    assert c(ph, None, 0, 4, 1, 1, None) == ND     # zero rows: s = 0 is still written
+    assert c(ph, 1, 4, 4, 4, 1, None) == ND
+    s = L.tsqr_mlp_mse
+    assert s(None, 1, 1, 1, 4, 4, 4, 1, None) == -1
+    assert s(ph, None, 1, 1, 4, 4, 4, 1, None) == -2
+    assert s(ph, 1, None, 1, 4, 4, 4, 1, None) == -3
+    assert s(ph, 1, 1, None, 4, 4, 4, 1, None) == -4
+    assert s(ph, 1, 1, 1, 0, 4, 4, 1, None) == -5
+    assert s(ph, 1, 1, 1, 4, 0, 4, 1, None) == -6
+    assert s(ph, 1, 1, 1, 4, 4, 3, 1, None) == -7
+    assert s(ph, 1, 1, 1, 4, 4, 4, None, None) == -8
+    assert s(ph, 1, 1, 1, 4, 4, 4, 1, None) == ND
+    a = L.tsqr_mlp_adam
+    args = (1e-3, 0.9, 0.999, 1e-8)
+    assert a(None, 1, 1, 1, 1, 4, *args, 1, None) == -1
+    assert a(ph, None, 1, 1, 1, 4, *args, 1, None) == -2
+    assert a(ph, 1, None, 1, 1, 4, *args, 1, None) == -3
+    assert a(ph, 1, 1, None, 1, 4, *args, 1, None) == -4
+    assert a(ph, 1, 1, 1, None, 4, *args, 1, None) == -5
+    assert a(ph, 1, 1, 1, 1, -1, *args, 1, None) == -6
+    assert a(ph, 1, 1, 1, 1, 4, *args, 0, None) == -11
+    assert a(ph, None, None, None, None, 0, *args, 1, None) == 0
+    assert a(ph, 1, 1, 1, 1, 4, *args, 1, None) == ND
+    fe = L.tsqr_surrogate_features
+    assert fe(None, 1, 4, 50, 1, None) == -1
+    assert fe(ph, None, 4, 50, 1, None) == -2
+    assert fe(ph, 1, -1, 50, 1, None) == -3
+    assert fe(ph, 1, 4, 0, 1, None) == -4
+    assert fe(ph, 1, 4, 65, 1, None) == -4
+    assert fe(ph, 1, 4, 50, None, None) == -5
+    assert fe(ph, None, 0, 50, None, None) == 0
+    assert fe(ph, 1, 4, 50, 1, None) == ND
+    t = L.tsqr_surrogate_targets
+    assert t(None, 1, 50, 1, 4, 50, 1, None) == -1
+    assert t(ph, None, 50, 1, 4, 50, 1, None) == -2
+    assert t(ph, 1, 49, 1, 4, 50, 1, None) == -3
+    assert t(ph, 1, 50, None, 4, 50, 1, None) == -4
+    assert t(ph, 1, 50, 1, -1, 50, 1, None) == -5
+    assert t(ph, 1, 50, 1, 4, 0, 1, None) == -6
+    assert t(ph, 1, 50, 1, 4, 50, None, None) == -7
+    assert t(ph, 1, 50, 1, 4, 50, 1, None) == ND
+    ap = L.tsqr_surrogate_apply
+    assert ap(None, 1, 1, 4, 50, 1, None) == -1
+    assert ap(ph, None, 1, 4, 50, 1, None) == -2
+    assert ap(ph, 1, None, 4, 50, 1, None) == -3
+    assert ap(ph, 1, 1, -1, 50, 1, None) == -4
+    assert ap(ph, 1, 1, 4, 0, 1, None) == -5
+    assert ap(ph, 1, 1, 4, 50, None, None) == -6
+    assert ap(ph, 1, 1, 4, 50, 1, None) == ND

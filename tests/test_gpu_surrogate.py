@@ -1,0 +1,293 @@
+"""The learned correction of the sampled preconditioner, through the C ABI.
+
+Its kernels (the BF16 matrix-core GEMM, the elementwise training steps, the
+feature, target and correction maps) are checked against plain numpy on the
+CPU: the GEMM within the FP32 summation bound on BF16-rounded operands,
+sequential sums, masks and biases bit for bit, the gradients of the whole
+network against an FP64 forward and backward pass that rounds the same
+operands to BF16.  The correction itself must leave the result the R of A whatever the
+network outputs: with a zero correction the path is bit for bit the sampled
+plan, and with an untrained network's arbitrary row scaling every instance
+still meets the mixed path's gates against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gates import GRAM64, kappa_of, row_gate64, row_scaled
+from paper_1002_4250_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1002_4250_amd import surrogate, tsqr  # noqa: E402
+
+EPS32 = 2.0 ** -24
+
+
+def bf16(x):
+    """FP32 -> BF16 (round to nearest even), returned as FP32 values."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def stored(rng, rows, cols, ld):
+    """A rows x cols matrix stored column-major with leading dimension ld
+    (padding rows filled too): (numpy (cols, ld) float32, the logical matrix)."""
+    S = rng.standard_normal((cols, ld)).astype(np.float32)
+    return S, S[:, :rows].T
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32).reshape(-1)).cuda()
+
+
+def gemm(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc):
+    h = tsqr.handle(0)
+    st = tsqr.lib().tsqr_gemm_bf16(h, ta, tb, M, N, K, alpha, A.data_ptr(), lda, B.data_ptr(), ldb, beta,
+                                   C.data_ptr(), ldc, tsqr._stream_ptr(torch, C.device))
+    assert st == 0
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (16, 16, 16), (37, 21, 45), (100, 3, 300), (5, 70, 17), (64, 48, 0)])
+def test_gemm_bf16_matches_numpy(ta, tb, M, N, K):
+    rng = np.random.default_rng(1000 * M + 10 * N + K + 5 * ta + 7 * tb)
+    ar, ac = (K, M) if ta else (M, K)
+    br, bc = (N, K) if tb else (K, N)
+    As, Al = stored(rng, ar, ac, ar + 3)
+    Bs, Bl = stored(rng, br, bc, br + 2)
+    Cs, C0 = stored(rng, M, N, M + 5)
+    opA = (Al.T if ta else Al).astype(np.float64)
+    opB = (Bl.T if tb else Bl).astype(np.float64)
+    alpha, beta = 0.75, -0.5
+    ref = alpha * (bf16(opA).astype(np.float64) @ bf16(opB)) + beta * C0
+    bound = (K + 4) * 2 * EPS32 * (abs(alpha) * (np.abs(bf16(opA)) @ np.abs(bf16(opB))) + abs(beta) * np.abs(C0))
+    Cd = dev(Cs)
+    gemm(ta, tb, M, N, K, alpha, dev(As), ar + 3, dev(Bs), br + 2, beta, Cd, M + 5)
+    Cg = Cd.cpu().numpy().reshape(N, M + 5)
+    assert np.all(np.abs(Cg[:, :M].T - ref) <= bound + 1e-30), (ta, tb, M, N, K)
+    assert np.array_equal(Cg[:, M:], Cs[:, M:])        # rows past M untouched
+    # beta = 0 never reads C (NaN there stays out of the result)
+    Cn = torch.full(((M + 5) * N,), float("nan"), device="cuda")
+    gemm(ta, tb, M, N, K, alpha, dev(As), ar + 3, dev(Bs), br + 2, 0.0, Cn, M + 5)
+    Cg = Cn.cpu().numpy().reshape(N, M + 5)[:, :M].T
+    assert np.all(np.abs(Cg - alpha * (bf16(opA).astype(np.float64) @ bf16(opB))) <= bound + 1e-30)
+
+
+def test_gemm_bf16_rounds_to_nearest_even():
+    """Operands exactly halfway between two BF16 values round to the even one:
+    1 + 2^-8 -> 1, 1 + 3 2^-8 -> 1 + 2^-6 (a 1 x 1 x 1 product against 1)."""
+    for x, want in [(1 + 2.0 ** -8, 1.0), (1 + 3 * 2.0 ** -8, 1 + 2.0 ** -6), (-(1 + 2.0 ** -8), -1.0),
+                    (1 + 2.0 ** -8 + 2.0 ** -20, 1 + 2.0 ** -7)]:
+        A, B, C = dev([x]), dev([1.0]), dev([0.0])
+        gemm(0, 0, 1, 1, 1, 1.0, A, 1, B, 1, 0.0, C, 1)
+        assert C.item() == want, (x, C.item())
+        assert bf16(np.array([x]))[0] == want
+
+
+def test_elementwise_kernels_bit_exact():
+    rng = np.random.default_rng(7)
+    h, s = tsqr.handle(0), tsqr._stream_ptr(torch, torch.device("cuda", 0))
+    L = tsqr.lib()
+    rows, cols, ld = 37, 11, 40
+    Zs, Z = stored(rng, rows, cols, ld)
+    bias = rng.standard_normal(cols).astype(np.float32)
+    for relu in (0, 1):
+        Zd = dev(Zs)
+        assert L.tsqr_mlp_bias_act(h, Zd.data_ptr(), rows, cols, ld, dev(bias).data_ptr(), relu, s) == 0
+        want = (Z + bias[None, :]).astype(np.float32)
+        if relu:
+            want = np.maximum(want, 0)
+        got = Zd.cpu().numpy().reshape(cols, ld)
+        assert np.array_equal(got[:, :rows].T, want) and np.array_equal(got[:, rows:], Zs[:, rows:])
+    Gs, G = stored(rng, rows, cols, ld)
+    out = np.where(rng.uniform(size=Zs.shape) < 0.5, 0.0, np.abs(Zs)).astype(np.float32)
+    Gd = dev(Gs)
+    assert L.tsqr_mlp_relu_grad(h, Gd.data_ptr(), dev(out).data_ptr(), rows, cols, ld, s) == 0
+    got = Gd.cpu().numpy().reshape(cols, ld)
+    assert np.array_equal(got[:, :rows].T, np.where(out[:, :rows].T > 0, G, 0).astype(np.float32))
+    # column sums in row order: the same FP32 additions in the same order
+    sd = torch.empty(cols, device="cuda")
+    assert L.tsqr_mlp_colsum(h, dev(Zs).data_ptr(), rows, cols, ld, sd.data_ptr(), s) == 0
+    acc = np.zeros(cols, dtype=np.float32)
+    for i in range(rows):
+        acc = (acc + Z[i]).astype(np.float32)
+    assert np.array_equal(sd.cpu().numpy(), acc)
+    # no rows: zero sums
+    assert L.tsqr_mlp_colsum(h, dev(Zs).data_ptr(), 0, cols, 1, sd.data_ptr(), s) == 0
+    assert np.array_equal(sd.cpu().numpy(), np.zeros(cols, dtype=np.float32))
+    # the loss gradient within two roundings, the loss within the FP32 sum bound
+    Ts, T = stored(rng, rows, cols, ld)
+    Dd, loss = dev(np.full(Zs.shape, 7.0)), torch.zeros(1, device="cuda")
+    assert L.tsqr_mlp_mse(h, dev(Zs).data_ptr(), dev(Ts).data_ptr(), Dd.data_ptr(), rows, cols, ld,
+                          loss.data_ptr(), s) == 0
+    d = (Z - T).astype(np.float32)
+    got = Dd.cpu().numpy().reshape(cols, ld)
+    assert np.allclose(got[:, :rows].T, 2.0 * d.astype(np.float64) / (rows * cols), rtol=2.5e-7, atol=0)
+    assert np.all(got[:, rows:] == 7.0)
+    want = float(np.sum(d.astype(np.float64) ** 2)) / (rows * cols)
+    assert abs(loss.item() - want) <= 1e-6 * want
+
+
+def test_adam_step_matches_numpy():
+    rng = np.random.default_rng(11)
+    h, s = tsqr.handle(0), tsqr._stream_ptr(torch, torch.device("cuda", 0))
+    count = 1000
+    f32 = lambda x: np.float32(x).astype(np.float64)    # noqa: E731  (the values the kernel sees)
+    p, g = f32(rng.standard_normal(count)), f32(rng.standard_normal(count))
+    m, v = f32(0.1 * rng.standard_normal(count)), f32(np.abs(0.01 * rng.standard_normal(count)))
+    pd, gd, md, vd = dev(p), dev(g), dev(m), dev(v)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    for step in (1, 2, 3):
+        assert tsqr.lib().tsqr_mlp_adam(h, pd.data_ptr(), gd.data_ptr(), md.data_ptr(), vd.data_ptr(), count, lr, b1,
+                                        b2, eps, step, s) == 0
+        B1, B2 = f32(b1), f32(b2)
+        m = B1 * m + (1 - B1) * g
+        v = B2 * v + (1 - B2) * g * g
+        p = p - lr * (m / (1 - B1 ** step)) / (np.sqrt(v / (1 - B2 ** step)) + eps)
+        assert np.allclose(md.cpu().numpy(), m, rtol=1e-6, atol=1e-7)
+        assert np.allclose(vd.cpu().numpy(), v, rtol=1e-6, atol=1e-12)
+        assert np.allclose(pd.cpu().numpy(), p, rtol=1e-6, atol=1e-4 * lr)
+
+
+def test_feature_target_and_correction_maps():
+    rng = np.random.default_rng(13)
+    batch, n = 21, 50
+    Rt = np.triu(rng.standard_normal((batch, n, n))) + np.eye(n)[None] * 3.0
+    R = Rt * np.exp(0.1 * rng.standard_normal((batch, n, 1))) * 1.7
+    Rt32 = np.ascontiguousarray(np.transpose(Rt, (0, 2, 1))).astype(np.float32)    # [b] column-major
+    R64 = np.ascontiguousarray(np.transpose(R, (0, 2, 1)))
+    Rtd = torch.from_numpy(Rt32).cuda()
+    X = surrogate.features(Rtd, batch, n).cpu().numpy().reshape(2 * n - 1, batch).T
+    Rt_ = Rt32.transpose(0, 2, 1).astype(np.float64)
+    d = np.log(np.abs(np.diagonal(Rt_, axis1=1, axis2=2)))
+    assert np.allclose(X[:, :n], d - d.mean(1, keepdims=True), rtol=0, atol=2e-5)
+    sup = np.stack([Rt_[:, i - 1, i] / np.abs(Rt_[:, i - 1, i - 1]) for i in range(1, n)], 1)
+    assert np.allclose(X[:, n:], sup, rtol=2.5e-7, atol=1e-30)
+    T = surrogate.targets(torch.from_numpy(R64).cuda(), Rtd, batch, n).cpu().numpy().reshape(n, batch).T
+    lr = np.log(np.abs(np.diagonal(R, axis1=1, axis2=2)) / np.abs(np.diagonal(Rt_, axis1=1, axis2=2)))
+    assert np.allclose(T, lr - lr.mean(1, keepdims=True), rtol=1e-6, atol=1e-7)
+    Y = 0.5 * rng.standard_normal((batch, n)).astype(np.float32)
+    Y[0, :4] = [3.0, -7.0, np.nan, np.inf]     # clamped to [-1, 1], a NaN to -1
+    Rp = surrogate.apply(Rtd, dev(Y.T), batch, n).cpu().numpy()
+    Yc = np.clip(np.nan_to_num(Y.astype(np.float64), nan=-1.0), -1.0, 1.0)
+    want = Rt32 * np.exp(Yc)[:, None, :]      # [b] column-major: row i is index [b, :, i]
+    assert np.allclose(Rp, want, rtol=1e-6, atol=0)
+
+
+def reference_grads(model, X, T, B):
+    """Forward and backward of the network in FP64 on the CPU, each GEMM operand
+    rounded to BF16 as the kernels round it."""
+    F, H, O = model.F, model.H, model.O
+    P = [p.cpu().numpy().astype(np.float64) for p in model.params]
+    W1, b1 = P[0].reshape(H, F).T, P[1]
+    W2, b2 = P[2].reshape(H, H).T, P[3]
+    W3, b3 = P[4].reshape(O, H).T, P[5]
+    r = lambda a: bf16(a).astype(np.float64)   # noqa: E731
+    Z1 = np.maximum(r(X) @ r(W1) + b1, 0)
+    Z2 = np.maximum(r(Z1) @ r(W2) + b2, 0)
+    Y = r(Z2) @ r(W3) + b3
+    dY = 2 * (Y - T) / (B * O)
+    gW3, gb3 = r(Z2).T @ r(dY), dY.sum(0)
+    dZ2 = (r(dY) @ r(W3).T) * (Z2 > 0)
+    gW2, gb2 = r(Z1).T @ r(dZ2), dZ2.sum(0)
+    dZ1 = (r(dZ2) @ r(W2).T) * (Z1 > 0)
+    gW1, gb1 = r(X).T @ r(dZ1), dZ1.sum(0)
+    return float(np.mean((Y - T) ** 2)), [gW1, gb1, gW2, gb2, gW3, gb3]
+
+
+@pytest.mark.parametrize("B", [37, 256])
+def test_mlp_gradients_match_cpu(B):
+    n = 50
+    model = surrogate.Mlp(2 * n - 1, n, H=256, seed=3, zero_output=False)
+    rng = np.random.default_rng(B)
+    X = rng.standard_normal((B, 2 * n - 1)).astype(np.float32)
+    T = (0.5 * rng.standard_normal((B, n))).astype(np.float32)
+    Y = model.forward(dev(X.T), B)
+    dY = model.mse(Y, dev(T.T), B)
+    model.backward(dY)
+    loss, ref = reference_grads(model, X.astype(np.float64), T.astype(np.float64), B)
+    assert abs(model.loss.item() - loss) <= 1e-3 * loss
+    shapes = [(model.H, model.F), None, (model.H, model.H), None, (model.O, model.H), None]
+    for k, (g, want) in enumerate(zip(model.grads, ref)):
+        got = g.cpu().numpy().astype(np.float64)
+        if shapes[k]:
+            got = got.reshape(shapes[k]).T
+        err = np.linalg.norm(got - want) / np.linalg.norm(want)
+        assert err < 2e-3, (k, err)
+
+
+def test_training_fits_the_sampled_rtilde():
+    """Adam through the library's kernels on features and targets gathered
+    from sampled plans: the loss falls, and on held-out batches the network
+    predicts the diagonal of R better than no correction does."""
+    n, m, batch, s = 50, 16384, 128, 256
+    plan = tsqr.MixedPlan(batch, m, n, sample_rows=s, seed=4)
+    train = surrogate.gather(plan, 32, seed=100)
+    held = surrogate.gather(plan, 4, seed=200)
+    model = surrogate.Mlp(2 * n - 1, n, H=256, seed=1)
+    # the untrained network is the zero correction
+    assert surrogate.predict_mse(model, held)[0] == surrogate.predict_mse(model, held)[1]
+    losses = surrogate.train(model, train, 600, minibatch=128, lr=1e-3, seed=2, log_every=100)
+    print("losses", losses)
+    assert losses[-1] < 0.8 * losses[0], losses
+    mse_model, mse_zero = surrogate.predict_mse(model, held)
+    print("held-out mse", mse_model, "zero correction", mse_zero)
+    # a 256-row sample of 16384: the network learns the part of the
+    # diagonal's error that R~ predicts (about 28% of it, measured)
+    assert np.isfinite(mse_model) and mse_model < 0.9 * mse_zero, (mse_model, mse_zero)
+
+
+def instance(flat, b, m, n):
+    return np.asfortranarray(flat[b * m * n:(b + 1) * m * n].reshape(n, m).T.astype(np.float64))
+
+
+def test_zero_correction_is_the_sampled_plan_bit_for_bit():
+    m, n, batch = 20000, 50, 6
+    flat, _ = inputs.conditioned_batch(batch, m, n, log10_kappa_max=8.0, seed=91)
+    Ad = torch.from_numpy(flat).cuda()
+    plan = tsqr.MixedPlan(batch, m, n, sample_rows=1024, seed=3)
+    R1, f1 = plan.run(Ad)
+    Rt = plan.rtilde().clone()
+    Rp = surrogate.apply(Rt, torch.zeros(batch * n, device="cuda"), batch, n)
+    assert torch.equal(Rp, Rt)
+    R2 = torch.empty_like(R1)
+    fl = torch.zeros(batch, dtype=torch.int32, device="cuda")
+    plan.launch_rtilde(Ad, Rp, R2, fl)
+    torch.cuda.synchronize()
+    assert torch.equal(R1, R2) and f1 == fl.cpu().tolist()
+    # the FP32 stage alone leaves the same R~
+    plan.launch_first_stage(Ad)
+    torch.cuda.synchronize()
+    assert torch.equal(plan.rtilde(), Rt)
+
+
+def test_learned_path_meets_the_gates_whatever_the_network():
+    """An untrained network scales the rows of R~ by arbitrary factors (up to
+    the clamp, e^{+-1}); the result is still the R of A on every instance
+    (the gates of the mixed path against the oracle)."""
+    m, n, batch = 20000, 50, 6
+    flat, kappas = inputs.conditioned_batch(batch, m, n, log10_kappa_max=8.0, seed=92)
+    Ad = torch.from_numpy(flat).cuda()
+    plan = tsqr.MixedPlan(batch, m, n, sample_rows=512, seed=8)
+    model = surrogate.Mlp(2 * n - 1, n, H=256, seed=5, zero_output=False)
+    R = torch.empty((batch, n, n), dtype=torch.float64, device="cuda")
+    fl = torch.zeros(batch, dtype=torch.int32, device="cuda")
+    Rp = surrogate.learned_launch(model, plan, Ad, R, fl)
+    torch.cuda.synchronize()
+    R, Rp = R.cpu().numpy(), Rp.cpu().numpy().astype(np.float64)
+    scale = np.exp(np.abs(np.log(np.abs(np.diagonal(Rp, axis1=1, axis2=2)))).max())
+    print("largest row factor (with R~'s own scale)", scale, "fallbacks", fl.cpu().tolist())
+    for b in range(batch):
+        A = instance(flat, b, m, n)
+        Ro = oracle.r_factor(A)
+        Rg = R[b].T
+        assert np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro) < 1e-13 * max(1.0, kappas[b]), b
+        assert oracle.gram_residual(A, Rg) < GRAM64, b
+        assert row_scaled(Rg, Ro) < row_gate64(kappa_of(Ro)), b
+        assert np.all(np.tril(Rg, -1) == 0) and np.all(np.diag(Rg) > 0), b
