@@ -9,7 +9,7 @@ which launches a small kernel that clears the tree counters and then the fused
 leaf+tree kernel.  Prints ONE JSON line on stdout; progress goes to stderr.
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 30] [--no-cpu-baseline] [--no-batched]
-        [--no-mixed] [--no-q] [--no-library] [--no-tuning]
+        [--no-mixed] [--no-learned] [--no-q] [--no-library] [--no-tuning]
 
 The warmup is long enough (about 50 ms of kernel time) for the GPU clocks to
 settle before the timed steps.  The handle follows the shipped tuning table
@@ -398,7 +398,7 @@ def time_batched(torch, tsqr, inputs, steps, warmup, n=50, count=4096, single_lo
     return out
 
 
-def time_mixed(torch, tsqr, inputs, steps, warmup, batch=256, m=1 << 16, n=50):
+def time_mixed(torch, tsqr, inputs, steps, warmup, batch=256, m=1 << 16, n=50, learned=True):
     """Conditioned batch stored in FP32: FP32 TSQR + FP64 correction vs the
     plain FP64 batched TSQR (on an FP64 copy) and the FP32 TSQR alone."""
     import concurrent.futures as cf
@@ -451,7 +451,8 @@ def time_mixed(torch, tsqr, inputs, steps, warmup, batch=256, m=1 << 16, n=50):
     Rts = ms_.rtilde().cpu().numpy()
     fallbacks_s = int(flags_s.sum().item())
     del ms_, Rs_d
-    learned = [learned_vs_sampled(torch, tsqr, Ad, batch, m, n, s_, timed, k, min(warmup, 3)) for s_ in (256, 4096)]
+    learned = [learned_vs_sampled(torch, tsqr, Ad, batch, m, n, s_, timed, k, min(warmup, 3))
+               for s_ in (256, 4096)] if learned else None
     sizes = np.full(batch, m, dtype=np.int64)
     offsets = np.arange(batch, dtype=np.int64) * m * n
     p32 = tsqr.BatchPlan(sizes, offsets, n, torch.float32)
@@ -589,6 +590,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned correction of the sampled R~ (its training launches many small kernels)")
     ap.add_argument("--no-q", action="store_true")
     ap.add_argument("--no-library", action="store_true", help="skip timing torch.linalg.qr beside the Q factor")
     ap.add_argument("--no-tuning", action="store_true", help="ignore the shipped tuning table")
@@ -643,7 +646,8 @@ def main():
 
     batched = None if args.no_batched else time_batched(torch, tsqr, inputs, args.steps, args.warmup,
                                                         single_loop=not args.no_single_loop)
-    mixed, mixed_data = (None, None) if args.no_mixed else time_mixed(torch, tsqr, inputs, args.steps, args.warmup)
+    mixed, mixed_data = (None, None) if args.no_mixed else time_mixed(torch, tsqr, inputs, args.steps, args.warmup,
+                                                                            learned=not args.no_learned)
     small = time_small(torch, tsqr, inputs)
     host = host_info()
 

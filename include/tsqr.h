@@ -373,9 +373,15 @@ int64_t tsqr_mixed_rtilde_offset(tsqr_mixed_plan_t plan);
  * The slot where a model can enter without changing the result is R~ (above):
  * these calls are the building blocks of a small MLP that maps features of a
  * sampled R~ to a correction of it, trained on the GPU.  All arrays are device
- * FP32, column-major with the given leading dimension; every call is
- * asynchronous on `stream` and allocates nothing.  Argument codes: -k for the
- * k-th argument; TSQR_ERR_NO_DEVICE on a planning handle.
+ * FP32, column-major with the given leading dimension, owned by the caller;
+ * every call is asynchronous on `stream` and allocates nothing.  The paper has
+ * no learned part: these calls serve the preconditioner above only.  Sizes are
+ * below 2^31.  A call whose output is empty (M or N, rows or cols, count or
+ * batch 0) returns 0 without a launch; tsqr_mlp_colsum with no rows writes
+ * zero sums, tsqr_gemm_bf16 with K = 0 writes beta C, and tsqr_mlp_mse needs
+ * rows, cols >= 1.  n is 1..TSQR_MAX_N for the feature, target and correction
+ * maps.  Argument
+ * codes: -k for the k-th argument; TSQR_ERR_NO_DEVICE on a planning handle.
  *
  * tsqr_gemm_bf16: C (M x N, ldc) = alpha op(A) op(B) + beta C with op(X) = X or
  *   X^T (ta, tb nonzero: stored transposed; op(A) is M x K, op(B) K x N).  A
