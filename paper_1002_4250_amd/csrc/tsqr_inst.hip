@@ -118,17 +118,28 @@ static hipError_t launch_qt_panel(const QtArgs<TSQR_INST_TAG>& x, int levels, hi
 hipError_t TSQR_QR_FN2(qt, TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL)(const QtArgs<TSQR_INST_TAG>& x, int levels,
                                                                     hipStream_t s)
 {
-    // panels of 48 columns in FP64 (12 slots of 8 rows stay in registers with
-    // the step's working set), 64 in FP32; one slot for k <= 4
-    constexpr int KW = sizeof(TSQR_INST_TAG) == 8 ? 12 : 16;
-    if (x.k <= 4) return x.k > 0 ? launch_qt_panel<1>(x, levels, s) : hipSuccess;
+    // panels of 52 columns in FP64 (13 slots of 8 rows stay in registers with
+    // the step's working set, no spills), 64 in FP32, so k = n = 50 takes one
+    // pass over the reflectors; a narrower panel takes 8, 4 or 1 slots (32, 16
+    // or 4 columns): a pass costs a fixed part (reading the reflectors and
+    // replaying their chain, about 1.1 ms at 2^22 x 50 in FP64) plus about
+    // 0.1 ms per slot
+    constexpr int KW = sizeof(TSQR_INST_TAG) == 8 ? 13 : 16;
+    if (x.k <= 0) return hipSuccess;
     hipError_t e = hipSuccess;
     for (int k0 = 0; k0 < x.k && e == hipSuccess; k0 += 4 * KW) {
         QtArgs<TSQR_INST_TAG> xp = x;
         xp.B = x.B + (int64_t)k0 * x.ldb;
         xp.C = x.C + (int64_t)k0 * x.ldc;
         xp.k = x.k - k0 < 4 * KW ? x.k - k0 : 4 * KW;
-        e = xp.k <= 4 ? launch_qt_panel<1>(xp, levels, s) : launch_qt_panel<KW>(xp, levels, s);
+        if (xp.k <= 4)
+            e = launch_qt_panel<1>(xp, levels, s);
+        else if (xp.k <= 16)
+            e = launch_qt_panel<4>(xp, levels, s);
+        else if (xp.k <= 32)
+            e = launch_qt_panel<8>(xp, levels, s);
+        else
+            e = launch_qt_panel<KW>(xp, levels, s);
     }
     return e;
 }

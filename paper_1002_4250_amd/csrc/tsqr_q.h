@@ -169,9 +169,10 @@ __global__ void __launch_bounds__(kWave) q_leaf_kernel(LeafTreeArgs<T> a, T* Q, 
 //   tree pass  (one launch per level, leaves first): a merge maps the stack
 //              [T_left; T_right] by its reflectors and keeps the top block.
 //   finish     C = D T_root, D the signs the root applied to R.
-// k is taken in panels (48 columns in FP64, 64 in FP32); KS column slots
-// (4 columns each) are compiled for k <= 4 and for the panel width.  The
-// per-leaf blocks are kQtCols = 64 columns wide.
+// k is taken in panels (52 columns in FP64, 64 in FP32); KS column slots
+// (4 columns each) are compiled for the panel width and for panels of at most
+// 32, 16 and 4 columns.  The per-leaf blocks are kQtCols = 64
+// columns wide.
 
 template <typename T, int NC, int RPL, int KS>
 __global__ void __launch_bounds__(kWave) qt_leaf_kernel(QtArgs<T> x)

@@ -36,7 +36,10 @@ def to_dev(A, dtype=torch.float64):
 @pytest.mark.parametrize("m,n,k,leaf_rows", [(256, 50, 1, 0), (256, 50, 7, 128), (5000, 17, 4, 0),
                                              (5000, 17, 5, 256), (70000, 50, 3, 0), (70000, 50, 48, 1000),
                                              (50, 50, 2, 0), (4097, 64, 49, 384), (1000, 1, 1, 0),
-                                             (9000, 32, 100, 128), (20000, 50, 64, 0)])
+                                             (9000, 32, 100, 128), (20000, 50, 64, 0), (3000, 50, 16, 0),
+                                             (3000, 50, 17, 256), (3000, 50, 50, 0), (3000, 50, 52, 512),
+                                             (3000, 50, 53, 0), (3000, 50, 69, 256), (3000, 50, 32, 0),
+                                             (3000, 50, 33, 512)])
 def test_apply_qt_matches_definition(m, n, k, leaf_rows):
     A = inputs.uniform(m, n, 41 + n)
     B = inputs.uniform(m, k, 43 + k)
@@ -79,12 +82,13 @@ def test_least_squares_from_apply_qt():
     assert np.array_equal(cv, c[:, 0])
 
 
-def test_apply_qt_fp32():
+@pytest.mark.parametrize("k", [5, 30, 50, 70])
+def test_apply_qt_fp32(k):
     """FP32 against the FP64 definition on the FP32-rounded inputs, at the
-    FP32 gate of the R factor (1e-5)."""
-    m, n, k = 20000, 50, 5
+    FP32 gate of the R factor (1e-5): panels of 16, 32 and 64 columns, and two."""
+    m, n = 20000, 50
     A = inputs.uniform(m, n, 61).astype(np.float32)
-    B = inputs.uniform(m, k, 62).astype(np.float32)
+    B = inputs.uniform(m, k, 62 + k).astype(np.float32)
     f = tsqr.Factorization(to_dev(A, torch.float32))
     C = f.apply_qt(to_dev(B, torch.float32)).cpu().numpy().astype(np.float64)
     Q = oracle.q_factor(A.astype(np.float64))
