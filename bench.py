@@ -278,6 +278,33 @@ def time_q(torch, tsqr, Ad, steps, warmup, library=True):
     }
 
 
+def schedule_from_stamps(np, st, khz):
+    """The batched launch's schedule from its per-workgroup (start, end)
+    clock stamps: the span, the most workgroups resident at once (the
+    slots), the busy fraction of slots x span, when the last workgroup
+    started (the dispatcher's queue is empty from then on) and how the slots
+    drain after it."""
+    st = st - st[:, 0].min()
+    start, end = st[:, 0] / khz, st[:, 1] / khz          # ms
+    span = float(end.max())
+    dur = end - start
+    t = np.concatenate([start, end])
+    d = np.concatenate([np.ones(len(st), np.int64), -np.ones(len(st), np.int64)])
+    o = np.lexsort((d, t))
+    active = np.cumsum(d[o])
+    slots = int(active.max())
+    full_at = float(t[o][int(np.argmax(active == slots))])
+    last_start = float(start.max())
+    drain = span - last_start
+    in_drain = np.clip(np.minimum(end, span) - np.maximum(start, last_start), 0.0, None).sum()
+    cap = slots * span
+    return {"span_ms": span, "slots": slots, "busy_fraction": float(dur.sum() / cap),
+            "all_slots_busy_at_ms": full_at, "last_start_ms": last_start, "drain_ms": drain,
+            "mean_busy_slots_in_drain": float(in_drain / drain) if drain > 0 else None,
+            "idle_fraction_in_drain": float((slots * drain - in_drain) / cap),
+            "idle_fraction_before_drain": float((slots * last_start - (dur.sum() - in_drain)) / cap)}
+
+
 def time_batched(torch, tsqr, inputs, steps, warmup, n=50, count=4096, single_loop=True):
     """The ragged batch: batched launch vs looped single-matrix calls (the
     loop, 8192 launches per pass, is skipped with single_loop=False, e.g.
@@ -307,6 +334,30 @@ def time_batched(torch, tsqr, inputs, steps, warmup, n=50, count=4096, single_lo
 
     ms_batched = timed(lambda: plan.run(Ad, R), steps, warmup)
     Rb = R.clone()
+    # the schedule, measured: launches with per-workgroup clock stamps (they
+    # cost no measurable time), back to back after plain ones as in the timed
+    # loop (a launch after an idle gap runs slower while the clocks ramp up);
+    # of the last three, the one with the median span is kept
+    khz = tsqr.device_clock_khz(tsqr.handle(0))
+    bufs = [torch.zeros((max(tiles, 1), 2), dtype=torch.int64, device="cuda") for _ in range(5)]
+    for _ in range(3):
+        plan.run(Ad, R)
+    for buf in bufs:
+        plan.run_stamped(Ad, R, buf)
+    torch.cuda.synchronize()
+    runs = []
+    for buf in bufs[2:]:
+        st = buf.cpu().numpy()
+        runs.append(((st[:, 1].max() - st[:, 0].min()) / khz, st))
+    del bufs
+    runs.sort(key=lambda r: r[0])
+    schedule = schedule_from_stamps(np, runs[1][1], khz)
+    schedule["spans_ms_of_3_launches"] = [float(r[0]) for r in runs]
+    schedule["same_R_as_plain_launch"] = bool(torch.equal(R, Rb))
+    log(f"batched schedule: span {schedule['span_ms']:.3f} ms on {schedule['slots']} slots, busy "
+        f"{100 * schedule['busy_fraction']:.1f}%; queue empty at {schedule['last_start_ms']:.3f} ms, then "
+        f"{schedule['drain_ms']:.3f} ms of drain at {schedule['mean_busy_slots_in_drain'] or 0:.0f} busy slots on average")
+
     # the batched launch captured in a HIP graph and replayed (checked against the eager result)
     ms_batched_graph = None
     try:
@@ -326,7 +377,6 @@ def time_batched(torch, tsqr, inputs, steps, warmup, n=50, count=4096, single_lo
         del gb
     except RuntimeError as e:
         log(f"graph capture of the batched launch failed: {e}")
-
     if not single_loop:
         sum_rows = int(sizes.sum())
         tflops = 2.0 * sum_rows * n * n / (ms_batched * 1e-3) / 1e12
@@ -335,7 +385,7 @@ def time_batched(torch, tsqr, inputs, steps, warmup, n=50, count=4096, single_lo
         torch.cuda.empty_cache()
         return {"workload": f"ragged batch {count} instances n={n} fp32", "value": count / (ms_batched * 1e-3),
                 "unit": "instances/s", "ms_per_step": ms_batched, "tiles": tiles, "leaf_rows": L,
-                "plain_loop": None}
+                "schedule": schedule, "plain_loop": None}
     # looped single-matrix calls over the same device data, one shared workspace
     h = tsqr.handle(0)
     views = [Ad[int(o):int(o) + int(m) * n].view(n, int(m)).t() for m, o in zip(sizes, offsets)]
@@ -381,7 +431,7 @@ def time_batched(torch, tsqr, inputs, steps, warmup, n=50, count=4096, single_lo
         "workload": f"ragged batch {count} instances m log-uniform [64, 65536] (sum {sum_rows}) n={n} fp32 "
                     "uniform[-1,1) seed 2",
         "value": count / (ms_batched * 1e-3), "unit": "instances/s", "ms_per_step": ms_batched,
-        "tiles": tiles, "leaf_rows": L,
+        "tiles": tiles, "leaf_rows": L, "schedule": schedule,
         "graph_replay": None if ms_batched_graph is None else
         {"value": count / (ms_batched_graph * 1e-3), "ms_per_step": ms_batched_graph, "steps": steps},
         "plain_loop": {"value": count / (ms_loop * 1e-3), "ms_per_step": ms_loop, "steps": loop_steps},

@@ -242,6 +242,21 @@ int tsqr_batch_plan_schedule(tsqr_batch_plan_t plan, int64_t *inst, int64_t *til
 int tsqr_batch_exec(tsqr_batch_plan_t plan, const void *A, void *R, int64_t ldr, void *ws, int64_t ws_bytes,
                     void *stream);
 
+/* tsqr_batch_exec that also measures its schedule: workgroup g (tile g of the
+ * plan's longest-first order, tsqr_batch_plan_info's tile count) writes the
+ * device's constant-rate clock when it starts and when it is done (its leaf
+ * and the merges it performed) to stamps[2g] and stamps[2g + 1] (device
+ * memory, 2 x tiles values, owned by the caller; ticks at
+ * tsqr_device_clock_khz kHz, arbitrary origin).  R is bit-identical to
+ * tsqr_batch_exec's.  Argument codes as tsqr_batch_exec's, plus -7 stamps. */
+int tsqr_batch_exec_stamped(tsqr_batch_plan_t plan, const void *A, void *R, int64_t ldr, void *ws, int64_t ws_bytes,
+                            uint64_t *stamps, void *stream);
+
+/* The rate of the clock of tsqr_batch_exec_stamped, in kHz (> 0); -1 for a
+ * NULL handle, -1000 - status otherwise (TSQR_ERR_NO_DEVICE on a planning
+ * handle, TSQR_ERR_HIP if the runtime cannot tell). */
+int64_t tsqr_device_clock_khz(tsqr_handle_t handle);
+
 /* ---- the Q factor --------------------------------------------------------------
  *
  * A = Q R with Q m x n with orthonormal columns (column-major, ldq >= m) and R

@@ -676,16 +676,26 @@ int tsqr_batch_plan_info(tsqr_batch_plan_t plan, int64_t* tiles, int64_t* leaves
     return 0;
 }
 
-int tsqr_batch_exec(tsqr_batch_plan_t plan, const void* A, void* R, int64_t ldr, void* ws, int64_t ws_bytes,
-                    void* stream)
+namespace {
+// Argument checks of tsqr_batch_exec, in argument order: 0, a negative code,
+// or 1 for a plan with nothing to do
+int batch_check(tsqr_batch_plan_t plan, const void* A, void* R, int64_t ldr, void* ws, int64_t ws_bytes)
 {
     if (!plan) return -1;
     if (plan->batch > 0 && plan->n > 0 && !A) return -2;
     if (plan->batch > 0 && plan->n > 0 && !R) return -3;
     if (ldr < (plan->n > 1 ? plan->n : 1)) return -4;
-    if (plan->batch == 0 || plan->n == 0) return 0;
+    if (plan->batch == 0 || plan->n == 0) return 1;
     if (!ws || (reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) != 0) return -5;
     if (ws_bytes < plan->ws_bytes) return -6;
+    return 0;
+}
+
+int batch_exec(tsqr_batch_plan_t plan, const void* A, void* R, int64_t ldr, void* ws, int64_t ws_bytes,
+               uint64_t* stamps, void* stream)
+{
+    const int rc = batch_check(plan, A, R, ldr, ws, ws_bytes);
+    if (rc) return rc > 0 ? 0 : rc;
     if (plan->h->planning_only) return TSQR_ERR_NO_DEVICE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     unsigned* tickets = static_cast<unsigned*>(ws);
@@ -702,6 +712,7 @@ int tsqr_batch_exec(tsqr_batch_plan_t plan, const void* A, void* R, int64_t ldr,
         a.tickets = tickets;
         a.R = static_cast<double*>(R);
         a.ldr = ldr;
+        a.stamps = stamps;
         e = dispatch_batch<double>(a, (int)plan->tiles, plan->nc, plan->rpl, s);
     } else {
         tsqr::BatchArgs<float> a;
@@ -714,9 +725,36 @@ int tsqr_batch_exec(tsqr_batch_plan_t plan, const void* A, void* R, int64_t ldr,
         a.tickets = tickets;
         a.R = static_cast<float*>(R);
         a.ldr = ldr;
+        a.stamps = stamps;
         e = dispatch_batch<float>(a, (int)plan->tiles, plan->nc, plan->rpl, s);
     }
     return hip_status(plan->h, e);
+}
+}  // namespace
+
+int tsqr_batch_exec(tsqr_batch_plan_t plan, const void* A, void* R, int64_t ldr, void* ws, int64_t ws_bytes,
+                    void* stream)
+{
+    return batch_exec(plan, A, R, ldr, ws, ws_bytes, nullptr, stream);
+}
+
+int tsqr_batch_exec_stamped(tsqr_batch_plan_t plan, const void* A, void* R, int64_t ldr, void* ws, int64_t ws_bytes,
+                            uint64_t* stamps, void* stream)
+{
+    const int rc = batch_check(plan, A, R, ldr, ws, ws_bytes);
+    if (rc) return rc > 0 ? 0 : rc;
+    if (!stamps) return -7;
+    return batch_exec(plan, A, R, ldr, ws, ws_bytes, stamps, stream);
+}
+
+int64_t tsqr_device_clock_khz(tsqr_handle_t h)
+{
+    if (!h) return -1;
+    if (h->planning_only) return -1000 - TSQR_ERR_NO_DEVICE;
+    int khz = 0;
+    const hipError_t e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device);
+    if (e != hipSuccess) return -1000 - hip_status(h, e);
+    return khz > 0 ? khz : -1000 - TSQR_ERR_HIP;
 }
 
 // ---- mixed precision: FP32 TSQR, then one FP64 correction --------------------

@@ -666,12 +666,16 @@ __global__ void __launch_bounds__(kWave) tsqr_leaf_tree_kernel(LeafTreeArgs<T> a
 //
 // With run_if set, the workgroups of an instance whose entry is 0 exit at once
 // (the mixed-precision fallback: only instances whose correction failed are
-// refactored, decided on the device).  TIn is the storage type of A.
+// refactored, decided on the device).  With stamps set, workgroup g writes
+// the constant-rate clock when it starts and when it is done (its leaf and
+// whatever merges it performed) to stamps[2g], stamps[2g + 1], which measures
+// the schedule.  TIn is the storage type of A.
 template <typename T, int NC, int RPL, typename TIn = T>
 __global__ void __launch_bounds__(kWave) tsqr_batch_kernel(BatchArgs<T, TIn> b)
 {
     __shared__ T Rs[Tri<NC>::kPadded];
     __shared__ T red[LdsScratch<NC>::kElems];
+    const uint64_t t_start = b.stamps ? (uint64_t)wall_clock64() : 0;
     const BatchTile t = b.tiles[blockIdx.x];
     if (b.run_if && b.run_if[t.inst] == 0) return;
     const BatchInstance in = b.inst[t.inst];
@@ -688,6 +692,10 @@ __global__ void __launch_bounds__(kWave) tsqr_batch_kernel(BatchArgs<T, TIn> b)
     a.ldr = b.ldr;
     a.qs = QStore<T>{};
     leaf_tree_body<T, NC, RPL, false, TIn>(a, t.leaf, Rs, red);
+    if (b.stamps && threadIdx.x == 0) {
+        b.stamps[2 * blockIdx.x] = t_start;
+        b.stamps[2 * blockIdx.x + 1] = (uint64_t)wall_clock64();
+    }
 }
 
 // ---- the paper's operator as a single-workgroup kernel -------------------------

@@ -66,6 +66,7 @@ struct BatchArgs {
     unsigned* tickets;
     T* R;                        // instance b's R at R + b * ldr * n
     int64_t ldr;
+    uint64_t* stamps = nullptr;  // null, or per workgroup: (start, end) on the device's constant-rate clock
 };
 
 using f64 = double;

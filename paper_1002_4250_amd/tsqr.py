@@ -54,6 +54,8 @@ SIGNATURES = [
     ("tsqr_batch_workspace_bytes", _i64, [_p]),
     ("tsqr_batch_plan_info", _i, [_p, _pi64, _pi64, _pi64]),
     ("tsqr_batch_exec", _i, [_p, _p, _p, _i64, _p, _i64, _p]),
+    ("tsqr_batch_exec_stamped", _i, [_p, _p, _p, _i64, _p, _i64, _p, _p]),
+    ("tsqr_device_clock_khz", _i64, [_p]),
     ("tsqr_qr_workspace_bytes", _i64, [_p, _i64, _i64, _i]),
     ("tsqr_geqr_qr_f64", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
     ("tsqr_geqr_qr_f32", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
@@ -385,6 +387,14 @@ def tsqr_batch_exec(plan, A, R, ldr, ws, ws_bytes, stream) -> int:
     return lib().tsqr_batch_exec(plan, A, R, ldr, ws, ws_bytes, stream)
 
 
+def device_clock_khz(handle) -> int:
+    """Rate of the device clock that ``BatchPlan.run_stamped`` reads, in kHz."""
+    v = lib().tsqr_device_clock_khz(handle)
+    if v <= 0:
+        raise TsqrError("tsqr_device_clock_khz", int(v) if v > -1000 else int(-1000 - v))
+    return int(v)
+
+
 class BatchPlan:
     """Plan + workspace for a ragged batch held in one flat device tensor
     (instance b is the m[b]-by-n column-major block at element offset
@@ -419,6 +429,25 @@ class BatchPlan:
                              self.ws.numel(), _stream_ptr(torch, self.dev))
         _check("tsqr_batch_exec", st, self.h)
         return R
+
+    def run_stamped(self, A_flat, R=None, stamps=None):
+        """``run`` that also measures the schedule: returns (R, stamps), stamps
+        an int64 device tensor (tiles, 2) of each workgroup's start and end
+        on the device clock (``device_clock_khz`` kHz, arbitrary origin), in
+        the plan's tile order."""
+        torch = self.torch
+        _check_flat(A_flat, "A", self.a_elems, self.dtype, self.dev)
+        if R is None:
+            R = torch.empty((self.batch, self.n, self.n), dtype=self.dtype, device=self.dev)
+        _check_flat(R, "R", self.batch * self.n * self.n, self.dtype, self.dev)
+        tiles = self.info()[0]
+        if stamps is None:
+            stamps = torch.zeros((max(tiles, 1), 2), dtype=torch.int64, device=self.dev)
+        _check_flat(stamps, "stamps", 2 * tiles, torch.int64, self.dev)
+        st = lib().tsqr_batch_exec_stamped(self.plan, A_flat.data_ptr(), R.data_ptr(), self.n, self.ws.data_ptr(),
+                                           self.ws.numel(), stamps.data_ptr(), _stream_ptr(torch, self.dev))
+        _check("tsqr_batch_exec_stamped", st, self.h)
+        return R, stamps
 
     def __del__(self):
         try:

@@ -668,3 +668,27 @@ def test_learned_correction_argument_checks(ph):
     assert ap(ph, 1, 1, 4, 0, 1, None) == -5
     assert ap(ph, 1, 1, 4, 50, None, None) == -6
     assert ap(ph, 1, 1, 4, 50, 1, None) == ND
+
+
+def test_batch_exec_stamped_argument_checks(ph):
+    """The stamped batch exec checks its arguments as tsqr_batch_exec does,
+    then the stamps (-7); the clock query needs a device."""
+    L = tsqr.lib()
+    p = tsqr.tsqr_batch_plan_create(ph, 2, 50, [300, 5000], [0, 300 * 50], None, tsqr.TSQR_F64)
+    try:
+        need = tsqr.tsqr_batch_workspace_bytes(p)
+        buf = ctypes.create_string_buffer(need + 512)
+        ws = (ctypes.addressof(buf) + 255) // 256 * 256
+        f = L.tsqr_batch_exec_stamped
+        assert f(None, 1, 1, 50, ws, need, 1, None) == -1
+        assert f(p, None, 1, 50, ws, need, 1, None) == -2
+        assert f(p, 1, None, 50, ws, need, 1, None) == -3
+        assert f(p, 1, 1, 49, ws, need, 1, None) == -4
+        assert f(p, 1, 1, 50, None, need, 1, None) == -5
+        assert f(p, 1, 1, 50, ws, need - 1, 1, None) == -6
+        assert f(p, 1, 1, 50, ws, need, None, None) == -7
+        assert f(p, 1, 1, 50, ws, need, 1, None) == tsqr.TSQR_ERR_NO_DEVICE
+    finally:
+        tsqr.tsqr_batch_plan_destroy(p)
+    assert L.tsqr_device_clock_khz(None) == -1
+    assert L.tsqr_device_clock_khz(ph) == -1000 - tsqr.TSQR_ERR_NO_DEVICE

@@ -63,3 +63,19 @@ def test_apply_synthetic_table_to_planning_handle(tmp_path):
         tsqr.tsqr_destroy(h)
         tsqr.tsqr_destroy(plain)
     assert autotune.load(str(tmp_path / "missing.json")) is None
+
+
+def test_schedule_from_stamps_on_a_known_schedule():
+    """Four slots: two 1 ms workgroups back to back on each, then one 2 ms
+    workgroup alone (clock at 100 MHz, arbitrary origin)."""
+    import importlib.util
+    import numpy as np
+    spec = importlib.util.spec_from_file_location("bench_module", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    st = np.array([(0, 1), (1, 2)] * 4 + [(2, 4)], dtype=np.int64) * 100000 + 12345
+    s = bench.schedule_from_stamps(np, st, 100000)
+    assert s["span_ms"] == 4.0 and s["slots"] == 4
+    assert s["busy_fraction"] == 10.0 / 16.0
+    assert s["last_start_ms"] == 2.0 and s["drain_ms"] == 2.0 and s["mean_busy_slots_in_drain"] == 1.0
+    assert s["idle_fraction_in_drain"] == 6.0 / 16.0 and s["idle_fraction_before_drain"] == 0.0

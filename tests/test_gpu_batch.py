@@ -178,3 +178,38 @@ def test_batch_in_hip_graph_matches_eager():
         assert torch.equal(R, eager), i
         plan.run(Ad)                 # eager work between replays
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_stamped_exec_measures_the_schedule(dt):
+    """The stamped exec gives R bit for bit as the plain exec, and a start and
+    end on the device clock for every workgroup: ends after starts, the span
+    close to the launch's own elapsed time, and no more workgroups at once
+    than the device holds."""
+    n = 50
+    flat, sizes, offsets = ragged(inputs.batched_sizes(300, lo=64, hi=40000, seed=9), n, 9, dt)
+    tdt = torch.float64 if dt == np.float64 else torch.float32
+    plan = tsqr.BatchPlan(sizes, offsets, n, tdt)
+    Ad = torch.from_numpy(flat).cuda()
+    R0 = plan.run(Ad).clone()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    R1, stamps = plan.run_stamped(Ad)
+    e1.record()
+    torch.cuda.synchronize()
+    assert torch.equal(R0, R1)
+    khz = tsqr.device_clock_khz(tsqr.handle(0))
+    st = stamps.cpu().numpy()
+    tiles = plan.info()[0]
+    assert st.shape == (tiles, 2)
+    assert np.all(st[:, 0] > 0) and np.all(st[:, 1] >= st[:, 0])
+    span_ms = (st[:, 1].max() - st[:, 0].min()) / khz
+    ev_ms = e0.elapsed_time(e1)
+    print(f"tiles {tiles}, clock {khz} kHz, span {span_ms:.3f} ms, events {ev_ms:.3f} ms", flush=True)
+    assert 0.5 * ev_ms < span_ms <= ev_ms * 1.05 + 0.05
+    # concurrency: +1 at each start, -1 at each end (ends first on ties)
+    t = np.concatenate([st[:, 0], st[:, 1]])
+    d = np.concatenate([np.ones(tiles, np.int64), -np.ones(tiles, np.int64)])
+    order = np.lexsort((d, t))
+    active = np.cumsum(d[order])
+    assert active.min() >= 0 and 1 <= active.max() <= 256 * 8
