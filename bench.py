@@ -113,6 +113,47 @@ def time_plain(torch, tsqr, Ad, steps, warmup):
     return ms_step, ms_kernel, wall, R
 
 
+def time_phases(torch, tsqr, Ad, flops):
+    """Where the FP64 kernel's time goes, from the per-leaf clock stamps of
+    tsqr_geqr_r_f64_stamped: launches run back to back after plain ones, as
+    in the timed loop (a launch after an idle gap runs slower while the
+    clocks come back up); of the last three, the one with the median span."""
+    import numpy as np
+    m, n = Ad.shape
+    h = tsqr.handle(0)
+    ws = tsqr.workspace(m, n, Ad.dtype)
+    R = torch.empty((n, n), dtype=Ad.dtype, device="cuda").t()
+    leaves = tsqr.tsqr_plan_info(h, m, n, tsqr.TSQR_F64)[1]
+    bufs = [torch.zeros((leaves, 4), dtype=torch.int64, device="cuda") for _ in range(5)]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in bufs]
+    for _ in range(20):
+        tsqr.geqr_r(Ad, R=R, ws=ws, h=h)
+    for buf, (a, b) in zip(bufs, ev):
+        a.record()
+        tsqr.geqr_r_stamped(Ad, R=R, ws=ws, h=h, stamps=buf)
+        b.record()
+    torch.cuda.synchronize()
+    khz = tsqr.device_clock_khz(h)
+    runs = []
+    for buf in bufs[2:]:
+        st = buf.cpu().numpy()
+        runs.append(((st[:, 2].max() - st[:, 0].min()) / khz, st))
+    runs.sort(key=lambda r: r[0])
+    st = runs[1][1]
+    t0 = st[:, 0].min()
+    leaf_end = (st[:, 1] - t0) / khz
+    root = int(np.argmax(st[:, 3] >= 100))
+    span = float((st[root, 2] - t0) / khz)
+    leaf_ms = float(leaf_end.max())
+    return {"span_ms": span, "starts_within_ms": float((st[:, 0].max() - t0) / khz),
+            "leaf_phase_ms": leaf_ms, "leaf_phase_end_min_ms": float(leaf_end.min()),
+            "tree_ms": span - leaf_ms, "tree_levels": int(st[root, 3] - 100),
+            "leaf_phase_TFLOPs": flops / (leaf_ms * 1e-3) / 1e12,
+            "leaf_phase_frac": flops / (leaf_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+            "spans_ms_of_3_launches": [float(r[0]) for r in runs],
+            "event_ms_of_the_same_3_launches": [a.elapsed_time(b) for a, b in ev[2:]]}
+
+
 def time_small(torch, tsqr, inputs, reps=200):
     """Latency of the small instance (m = 256, n = 50, FP64, seed 0; the
     automatic policy gives two leaves of 128 rows, so one chunk per leaf and
@@ -682,6 +723,10 @@ def main():
     gbs = nbytes / (ms_kernel * 1e-3) / 1e9
     log(f"fp64: {ms_step * 1e3:.1f} us/step, kernel {ms_kernel * 1e3:.1f} us, {tflops:.2f} TFLOP/s, {gbs:.0f} GB/s")
     R64 = R.cpu().numpy()
+    phases = time_phases(torch, tsqr, Ad, flops)
+    log(f"fp64 phases: leaves done at {phases['leaf_phase_end_min_ms'] * 1e3:.0f}-{phases['leaf_phase_ms'] * 1e3:.0f} us "
+        f"({phases['leaf_phase_TFLOPs']:.1f} TFLOP/s), then the tree's {phases['tree_levels']} levels "
+        f"{phases['tree_ms'] * 1e3:.0f} us")
     qf = None if args.no_q else time_q(torch, tsqr, Ad, args.steps, args.warmup, library=not args.no_library)
 
     # FP32 variant of the same workload (input = RNE rounding of the FP64 draws)
@@ -764,7 +809,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": tflops / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "kernel": "tsqr_leaf_tree_kernel<double,50>", "kernel_ms": ms_kernel,
-                     "hbm_GBs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS},
+                     "hbm_GBs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS, "phases": phases},
         "cpu_baseline": cpu,
         "cpu_baseline_all_cores": cpu_all,
         "host": host,

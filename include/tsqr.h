@@ -157,6 +157,18 @@ int tsqr_geqr_r_f64(tsqr_handle_t handle, int64_t m, int64_t n, const double *A,
 int tsqr_geqr_r_f32(tsqr_handle_t handle, int64_t m, int64_t n, const float *A, int64_t lda,
                     float *R, int64_t ldr, void *ws, int64_t ws_bytes, void *stream);
 
+/* tsqr_geqr_r_f64 that also measures where the time goes: lane 0 of leaf i's
+ * wavefront writes, to stamps[4i .. 4i+3] (device memory owned by the caller,
+ * 4 x leaves values, leaves from tsqr_plan_info): the device's constant-rate
+ * clock (tsqr_device_clock_khz) when it starts, when its leaf phase (step 1
+ * of section 2) is done and when it exits, and the tree level at which it
+ * stopped (the first to arrive at a merge stops there), plus 100 for the
+ * wavefront that finished the root.  R is
+ * bit-identical to tsqr_geqr_r_f64's.  Argument codes as tsqr_geqr_r_f64's,
+ * plus -10 stamps. */
+int tsqr_geqr_r_f64_stamped(tsqr_handle_t handle, int64_t m, int64_t n, const double *A, int64_t lda, double *R,
+                            int64_t ldr, void *ws, int64_t ws_bytes, uint64_t *stamps, void *stream);
+
 /* For callers that cannot allocate device memory or pass a workspace (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): tsqr_geqr_r_f64 with the workspace taken from a fixed array that

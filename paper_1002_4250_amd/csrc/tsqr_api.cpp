@@ -231,7 +231,7 @@ hipError_t dispatch_op(int n, int nc, T* R1, T* R2, T* tau, hipStream_t s)
 
 template <typename T>
 int geqr_r(tsqr_handle_t h, int64_t m, int64_t n, const T* A, int64_t lda, T* R, int64_t ldr, void* ws,
-           int64_t ws_bytes, void* stream, int dtype)
+           int64_t ws_bytes, void* stream, int dtype, bool stamped = false, uint64_t* stamps = nullptr)
 {
     if (!h) return -1;
     if (m < 0) return -2;
@@ -247,9 +247,11 @@ int geqr_r(tsqr_handle_t h, int64_t m, int64_t n, const T* A, int64_t lda, T* R,
     if (!ws) return -8;
     if (ws_bytes < g.ws_bytes) return -9;
     if ((reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) != 0) return -8;
+    if (stamped && !stamps) return -10;
     if (h->planning_only) return TSQR_ERR_NO_DEVICE;
 
     tsqr::LeafTreeArgs<T> a;
+    a.stamps = stamps;
     a.A = A;
     a.m = m;
     a.lda = lda;
@@ -455,6 +457,12 @@ int tsqr_geqr_r_f64(tsqr_handle_t handle, int64_t m, int64_t n, const double* A,
                     int64_t ldr, void* ws, int64_t ws_bytes, void* stream)
 {
     return geqr_r<double>(handle, m, n, A, lda, R, ldr, ws, ws_bytes, stream, TSQR_F64);
+}
+
+int tsqr_geqr_r_f64_stamped(tsqr_handle_t handle, int64_t m, int64_t n, const double* A, int64_t lda, double* R,
+                            int64_t ldr, void* ws, int64_t ws_bytes, uint64_t* stamps, void* stream)
+{
+    return geqr_r<double>(handle, m, n, A, lda, R, ldr, ws, ws_bytes, stream, TSQR_F64, true, stamps);
 }
 
 int tsqr_geqr_r_f64_noalloc(tsqr_handle_t handle, int64_t m, int64_t n, const double* A, int64_t lda, double* R,

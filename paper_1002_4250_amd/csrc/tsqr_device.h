@@ -504,7 +504,11 @@ __device__ __forceinline__ void triangle_to_lds(const T* __restrict__ src, T* ds
 // output); `leaf` is this workgroup's leaf.  With WQ (the Q-factor mode) the
 // leaf also writes its reflectors (a.qs.V, a.qs.tau_leaf), every merge those
 // of the operator (a.qs.Vn, a.qs.tau_node), and the root the sign pattern of
-// R's diagonal as the starting block of Q (a.qs.qblk, slot 0).
+// R's diagonal as the starting block of Q (a.qs.qblk, slot 0).  With
+// a.stamps set, lane 0 writes the constant-rate clock at the start, at the
+// end of the leaf phase and at exit, and the tree level at which it stopped
+// (plus 100 for the root), to a.stamps[4 leaf + 0..3]: the split of the time
+// between the leaves and the tree, measured.
 template <typename T, int NC, int RPL, bool WQ = false, typename TIn = T>
 __device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T, TIn>& a, int leaf, T* Rs, T* red)
 {
@@ -515,6 +519,7 @@ __device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T, TIn>& a, in
     const int q = lane >> 4, p = lane & 15;
     const int64_t r0 = (int64_t)leaf * a.leaf_rows;
     const int64_t r1 = (r0 + a.leaf_rows < a.m) ? r0 + a.leaf_rows : a.m;
+    const uint64_t t_start = a.stamps ? (uint64_t)wall_clock64() : 0;
 
     for (int i = lane; i < NT; i += kWave) Rs[i] = T(0);
 
@@ -549,6 +554,10 @@ __device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T, TIn>& a, in
         }
     }
     wave_sync();
+    if (a.stamps && lane == 0) {
+        a.stamps[4 * leaf] = t_start;
+        a.stamps[4 * leaf + 1] = (uint64_t)wall_clock64();
+    }
 
     // step 2: binary reduction tree across leaves
     const int P = a.leaves;
@@ -574,7 +583,13 @@ __device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T, TIn>& a, in
         unsigned old = 0;
         if (lane == 0) old = atomicAdd(&a.tickets[id], 1u);
         old = (unsigned)__builtin_amdgcn_readfirstlane((int)old);
-        if (old == 0) return;                   // the partner will merge
+        if (old == 0) {                         // the partner will merge
+            if (a.stamps && lane == 0) {
+                a.stamps[4 * leaf + 2] = (uint64_t)wall_clock64();
+                a.stamps[4 * leaf + 3] = (uint64_t)level;
+            }
+            return;
+        }
         __threadfence();
         if (lane == 0) a.tickets[id] = 0u;      // both arrived: reset for the next call
 
@@ -624,6 +639,10 @@ __device__ __forceinline__ void leaf_tree_body(const LeafTreeArgs<T, TIn>& a, in
             if (__builtin_signbit(Rs[Tri<NC>::off(i)])) v = -v;
         }
         a.R[i + (int64_t)k * a.ldr] = v;
+    }
+    if (a.stamps && lane == 0) {
+        a.stamps[4 * leaf + 2] = (uint64_t)wall_clock64();
+        a.stamps[4 * leaf + 3] = (uint64_t)(100 + level);
     }
     if constexpr (WQ) {
         // R = D R_raw with D the diagonal of signs, so Q = Q_raw D: the tree

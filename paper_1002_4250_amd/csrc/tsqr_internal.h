@@ -36,6 +36,7 @@ struct LeafTreeArgs {
     T* R;                 // n-by-n output
     int64_t ldr;
     QStore<T> qs;         // Q-factor mode only
+    uint64_t* stamps = nullptr;  // null, or per leaf: start, leaf phase done, exit, level stopped at (+100: root)
 };
 
 // Batched execution: per-instance description and the (instance, leaf) tiles.

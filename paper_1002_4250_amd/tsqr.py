@@ -45,6 +45,7 @@ SIGNATURES = [
     ("tsqr_rows_per_lane_compiled", _i64, [_i, _i64, _pi64, _i64]),
     ("tsqr_workspace_bytes", _i64, [_p, _i64, _i64, _i]),
     ("tsqr_geqr_r_f64", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
+    ("tsqr_geqr_r_f64_stamped", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p, _p]),
     ("tsqr_geqr_r_f32", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
     ("tsqr_geqr_r_f64_noalloc", _i, [_p, _i64, _i64, _p, _i64, _p, _i64, _p]),
     ("tsqr_qr_uppers_f64", _i, [_p, _i64, _p, _p, _p, _p]),
@@ -305,6 +306,33 @@ def geqr_r(A, R=None, ws=None, h=None):
             _stream_ptr(torch, dev))
     _check(fn.__name__, st, h)
     return R
+
+
+def geqr_r_stamped(A, R=None, ws=None, h=None, stamps=None):
+    """``geqr_r`` for a float64 A that also measures where the time goes:
+    returns (R, stamps), stamps an int64 device tensor (leaves, 4): per leaf
+    its start, the end of its leaf phase and its exit on the device clock
+    (``device_clock_khz`` kHz, arbitrary origin), and the tree level at
+    which it stopped (plus 100 for the root)."""
+    import torch
+    if A.dtype != torch.float64 or not A.is_cuda:
+        raise TypeError("A must be a float64 device tensor")
+    m, n, lda = _col_major(A)
+    dev = A.device
+    h = h or handle(dev.index or 0)
+    if R is None:
+        R = torch.empty((n, n), dtype=A.dtype, device=dev).t()
+    ldr = _check_matrix(R, "R", n, n, A.dtype, dev)
+    if ws is None:
+        ws = workspace(m, n, A.dtype, dev, h)
+    leaves = tsqr_plan_info(h, m, n, TSQR_F64)[1] if n else 0
+    if stamps is None:
+        stamps = torch.zeros((max(leaves, 1), 4), dtype=torch.int64, device=dev)
+    _check_flat(stamps, "stamps", 4 * leaves, torch.int64, dev)
+    st = lib().tsqr_geqr_r_f64_stamped(h, m, n, A.data_ptr(), lda, R.data_ptr(), ldr, ws.data_ptr(),
+                                       _ws_bytes(ws, dev), stamps.data_ptr(), _stream_ptr(torch, dev))
+    _check("tsqr_geqr_r_f64_stamped", st, h)
+    return R, stamps
 
 
 def qr_uppers(R1, R2, tau=None, h=None):

@@ -692,3 +692,22 @@ def test_batch_exec_stamped_argument_checks(ph):
         tsqr.tsqr_batch_plan_destroy(p)
     assert L.tsqr_device_clock_khz(None) == -1
     assert L.tsqr_device_clock_khz(ph) == -1000 - tsqr.TSQR_ERR_NO_DEVICE
+
+
+def test_geqr_r_stamped_argument_checks(ph):
+    """tsqr_geqr_r_f64's argument codes, then -10 for the stamps."""
+    L = tsqr.lib()
+    m, n = 1 << 20, 50
+    need = tsqr.tsqr_workspace_bytes(ph, m, n, tsqr.TSQR_F64)
+    f = L.tsqr_geqr_r_f64_stamped
+    assert f(None, m, n, 1, m, 1, n, 256, need, 1, None) == -1
+    assert f(ph, -1, n, 1, m, 1, n, 256, need, 1, None) == -2
+    assert f(ph, m, -1, 1, m, 1, n, 256, need, 1, None) == -3
+    assert f(ph, m, n, None, m, 1, n, 256, need, 1, None) == -4
+    assert f(ph, m, n, 1, m - 1, 1, n, 256, need, 1, None) == -5
+    assert f(ph, m, n, 1, m, None, n, 256, need, 1, None) == -6
+    assert f(ph, m, n, 1, m, 1, n - 1, 256, need, 1, None) == -7
+    assert f(ph, m, n, 1, m, 1, n, None, need, 1, None) == -8
+    assert f(ph, m, n, 1, m, 1, n, 256, need - 1, 1, None) == -9
+    assert f(ph, m, n, 1, m, 1, n, 256, need, None, None) == -10
+    assert f(ph, m, n, 1, m, 1, n, 256, need, 1, None) == tsqr.TSQR_ERR_NO_DEVICE

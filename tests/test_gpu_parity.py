@@ -320,3 +320,38 @@ def test_mixed_and_batch_argument_errors_with_device():
         tsqr.tsqr_mixed_plan_destroy(p)
     with pytest.raises(tsqr.TsqrError):
         tsqr.MixedPlan(1, 100, 65)
+
+
+@pytest.mark.parametrize("m,leaf_rows", [(1 << 20, 0), (5 * 1024 + 300, 1024)])
+def test_stamped_call_measures_leaves_and_tree(m, leaf_rows):
+    """The stamped call gives R bit for bit as the plain one, and for every
+    leaf a start, the end of its leaf phase and its exit in that order; the
+    tree's shape shows in the levels the wavefronts stopped at (a balanced
+    binary tree for a power-of-two leaf count, exactly one root)."""
+    n = 50
+    A = inputs.uniform(m, n, 77)
+    h = tsqr.handle(0)
+    tsqr.tsqr_set_option(h, tsqr.TSQR_OPT_LEAF_ROWS, leaf_rows)
+    try:
+        Ad = to_dev(A)
+        R0 = tsqr.geqr_r(Ad).clone()
+        R1, stamps = tsqr.geqr_r_stamped(Ad)
+        torch.cuda.synchronize()
+        P = tsqr.tsqr_plan_info(h, m, n, tsqr.TSQR_F64)[1]
+    finally:
+        tsqr.tsqr_set_option(h, tsqr.TSQR_OPT_LEAF_ROWS, 0)
+    assert torch.equal(R0, R1)
+    st = stamps.cpu().numpy()[:P]
+    assert np.all(st[:, 0] > 0) and np.all(st[:, 1] >= st[:, 0]) and np.all(st[:, 2] >= st[:, 1])
+    levels = math.ceil(math.log2(P)) if P > 1 else 0
+    roots = np.flatnonzero(st[:, 3] >= 100)
+    assert len(roots) == 1 and st[roots[0], 3] == 100 + levels
+    # the root finishes last
+    assert st[roots[0], 2] == st[:, 2].max()
+    stop = st[:, 3] % 100
+    if P & (P - 1) == 0:
+        counts = np.bincount(stop, minlength=levels + 1)
+        assert counts.tolist() == [P >> (k + 1) for k in range(levels)] + [1], counts
+    khz = tsqr.device_clock_khz(h)
+    print(f"P={P}: leaf phase {(st[:, 1].max() - st[:, 0].min()) / khz * 1e3:.1f} us, "
+          f"tree {(st[roots[0], 2] - st[:, 1].max()) / khz * 1e3:.1f} us", flush=True)
