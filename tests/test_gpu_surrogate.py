@@ -291,3 +291,27 @@ def test_learned_path_meets_the_gates_whatever_the_network():
         assert oracle.gram_residual(A, Rg) < GRAM64, b
         assert row_scaled(Rg, Ro) < row_gate64(kappa_of(Ro)), b
         assert np.all(np.tril(Rg, -1) == 0) and np.all(np.diag(Rg) > 0), b
+
+
+@pytest.mark.parametrize("bad", ["zero", "nan"])
+def test_caller_rtilde_that_is_singular_or_nan_falls_back(bad):
+    """A caller's R~ that cannot precondition (all zero, or NaN) sends every
+    instance to the FP64 path, whose R meets the gates."""
+    m, n, batch = 4096, 50, 3
+    flat, kappas = inputs.conditioned_batch(batch, m, n, log10_kappa_max=4.0, seed=93)
+    Ad = torch.from_numpy(flat).cuda()
+    plan = tsqr.MixedPlan(batch, m, n, sample_rows=512, seed=2)
+    Rt = torch.zeros((batch, n, n), dtype=torch.float32, device="cuda")
+    if bad == "nan":
+        Rt.fill_(float("nan"))
+    R = torch.empty((batch, n, n), dtype=torch.float64, device="cuda")
+    fl = torch.zeros(batch, dtype=torch.int32, device="cuda")
+    plan.launch_rtilde(Ad, Rt, R, fl)
+    torch.cuda.synchronize()
+    assert fl.cpu().tolist() == [1] * batch
+    R = R.cpu().numpy()
+    for b in range(batch):
+        A = instance(flat, b, m, n)
+        Ro = oracle.r_factor(A)
+        assert np.linalg.norm(R[b].T - Ro) / np.linalg.norm(Ro) < 1e-13 * max(1.0, kappas[b]), b
+        assert oracle.gram_residual(A, R[b].T) < GRAM64, b
