@@ -425,7 +425,9 @@ int64_t tsqr_mixed_rtilde_offset(tsqr_mixed_plan_t plan);
  *   >= 1 for the bias corrections.
  * tsqr_surrogate_features: for a batch of R~ (instance b at Rt + b*n*n, ld n),
  *   X (batch x (2n - 1), ld batch): log|R~(i,i)| minus its mean over i, then
- *   R~(i-1, i)/|R~(i-1, i-1)| for i = 1..n-1.
+ *   R~(i-1, i)/|R~(i-1, i-1)| for i = 1..n-1.  A zero diagonal entry makes
+ *   the instance's features non-finite; the correction then clamps what the
+ *   network gives (below), and the guard of the FP64 pass decides.
  * tsqr_surrogate_targets: Y (batch x n, ld batch) = log(|R(i,i)|/|R~(i,i)|)
  *   minus its mean over i, R the FP64 R of all of A (instance b at R + b*ldr*n).
  * tsqr_surrogate_apply: Rout = R~ with row i scaled by exp(Y(b, i)), Y(b, i)
