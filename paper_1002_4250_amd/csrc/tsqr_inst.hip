@@ -21,8 +21,14 @@ namespace tsqr {
 hipError_t TSQR_LEAF_FN2(TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL)(const LeafTreeArgs<TSQR_INST_TAG>& a,
                                                                      hipStream_t s)
 {
-    hipLaunchKernelGGL((dev::tsqr_leaf_tree_kernel<TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL>), dim3(a.leaves),
-                       dim3(dev::kWave), 0, s, a);
+    // four leaves per workgroup where the leaf count allows: the two lowest
+    // tree levels then meet in LDS
+    if (a.leaves >= 4 && a.leaves % 4 == 0)
+        hipLaunchKernelGGL((dev::tsqr_leaf_tree4_kernel<TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL>),
+                           dim3(a.leaves / 4), dim3(4 * dev::kWave), 0, s, a);
+    else
+        hipLaunchKernelGGL((dev::tsqr_leaf_tree_kernel<TSQR_INST_TAG, TSQR_INST_NC, TSQR_INST_RPL>), dim3(a.leaves),
+                           dim3(dev::kWave), 0, s, a);
     return hipGetLastError();
 }
 #define TSQR_OCC_FN(tag, nc, rpl) occupancy_leaf_##tag##_##nc##_##rpl
