@@ -808,7 +808,8 @@ def main():
                    "tuning_table_entries": tuned},
         "roofline": {"bound": "alu", "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": tflops / PEAK_FP64_TFLOPS, "traffic": traffic,
-                     "kernel": "tsqr_leaf_tree_kernel<double,50>", "kernel_ms": ms_kernel,
+                     "kernel": ("tsqr_leaf_tree4_kernel<double,50,8>" if leaves % 4 == 0 and leaves >= 4
+                                else "tsqr_leaf_tree_kernel<double,50,8>"), "kernel_ms": ms_kernel,
                      "hbm_GBs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS, "phases": phases},
         "cpu_baseline": cpu,
         "cpu_baseline_all_cores": cpu_all,
